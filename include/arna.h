@@ -1,0 +1,192 @@
+/*
+ * arna.h -- C interface of the MI355X (gfx950) particle-filter step with
+ * RNA / ARNA distributed resampling.
+ *
+ * Method: Demirel, Smal, Niessen, Meijering, Sbalzarini, "An Adaptive
+ * Distributed Resampling Algorithm with Non-Proportional Allocation"
+ * (arXiv:1310.4624).  One call of pf_step is one iteration of Alg. 3 (ARNA)
+ * or Alg. 2 (RNA): ring, exchange ratio, particle exchange, renormalization,
+ * (P) and (U) of Alg. 1, per-PE estimate and weight, local systematic
+ * resampling, weight reset, master estimate.  A processing element (PE) is
+ * one GPU workgroup that owns a fixed block of N_p particles (Sec. III-A).
+ *
+ * Conventions for every entry point:
+ *   - Return value: PF_OK (0) or a negative PF_E* code; nothing throws across
+ *     this interface.  pf_strerror() gives the text.
+ *   - "device" pointers are HIP device memory (e.g. torch CUDA tensors on
+ *     ROCm); "host" pointers are ordinary CPU memory.  The caller owns every
+ *     pointer it passes; the library owns all particle buffers.
+ *   - Work is enqueued on pf_config.stream (NULL = the default stream).  Only
+ *     pf_estimate, pf_debug_* and pf_destroy synchronize with the host.
+ *   - Particle state is float32 and component-major: [5][N] for
+ *     (x, y, vx, vy, I), N = n_filters * n_pe * n_per_pe; slot (f, m, s) is
+ *     column ((f * n_pe) + m) * n_per_pe + s.  x is the image column, y the
+ *     row; pixel (u, v) has its centre at (u, v).
+ */
+#ifndef ARNA_H
+#define ARNA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PF_OK = 0,
+    PF_EINVAL = -1,        /* bad argument or configuration */
+    PF_ENOMEM = -2,        /* device allocation failed */
+    PF_EHIP = -3,          /* a HIP runtime call failed */
+    PF_ENUMERIC = -4,      /* a log-weight was NaN (e.g. a NaN pixel); sticky */
+    PF_ESTATE = -5,        /* call out of order (e.g. pf_exchange twice) */
+    PF_EUNSUPPORTED = -6   /* size beyond the limits below */
+};
+
+enum { PF_MODE_RNA = 0, PF_MODE_ARNA = 1 };
+enum { PF_INIT_TRACKING = 0, PF_INIT_INFOSHARE = 1 };
+enum { PF_LIK_PATCH = 0, PF_LIK_POINT = 1 };
+
+/* Debug flags (pf_config.debug). */
+enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the last step */
+       PF_DEBUG_LINEAGE = 2   /* carry an int32 lineage tag per particle */ };
+
+/* Limits of this build. */
+#define PF_MAX_PE 8192u
+#define PF_MAX_PER_PE 4096u
+#define PF_MAX_PATCH 15u
+
+typedef struct pf_ctx pf_ctx;   /* opaque; created by pf_init, freed by pf_destroy */
+
+typedef struct {
+    uint32_t struct_size;       /* = sizeof(pf_config); ABI check */
+    uint32_t n_filters;         /* F: independent filters (one tracked object each) */
+    uint32_t n_pe;              /* M: PEs per filter, 1..PF_MAX_PE */
+    uint32_t n_per_pe;          /* N_p: particles per PE, 1..PF_MAX_PER_PE */
+    uint32_t width, height;     /* frame size in pixels (patch mode) */
+    uint32_t patch;             /* odd patch side, 1..PF_MAX_PATCH (9 in the benchmarks) */
+    uint32_t mode;              /* PF_MODE_RNA: fixed ring, N_ex = floor(fixed_ratio N_p)
+                                   PF_MODE_ARNA: random ring (Sec. IV-B), N_ex by Eq. 3 */
+    uint32_t init_mode;         /* PF_INIT_TRACKING or PF_INIT_INFOSHARE (Sec. V) */
+    uint32_t lik_mode;          /* PF_LIK_PATCH (image) or PF_LIK_POINT (position data) */
+    float fixed_ratio;          /* RNA exchange ratio N_ex/N_p, in [0, 1] */
+    float initial_ratio;        /* ARNA ratio of the first iteration, in [0, 1] */
+    float eff_cutoff;           /* ARNA: no exchange when PE_eff > eff_cutoff * M;
+                                   values outside (0, 1) disable the cut-off */
+    float psf_sigma;            /* spot profile width (px), > 0 */
+    float background;           /* image background level */
+    float noise_sigma;          /* pixel noise std (patch) or position noise std (point), > 0 */
+    float q;                    /* NCV process-noise intensity (px^2), >= 0 */
+    float sigma_I;              /* intensity random-walk std, >= 0 */
+    uint32_t debug;             /* PF_DEBUG_* flags */
+    uint64_t seed;              /* Philox key */
+    void *stream;               /* hipStream_t or NULL */
+} pf_config;
+
+/* Host-side result of pf_estimate.  Arrays are caller-allocated; every
+ * pointer except x_global may be NULL. */
+typedef struct {
+    double *x_global;           /* [F][5] master estimate x_k (Alg. 3, last step) */
+    double *x_pe;               /* [F][M][5] per-PE estimates x^m_k */
+    double *log_mass_pe;        /* [F][M] log W^(m)_k */
+    double *log_mass_glob;      /* [F] log W_k = log sum_m W^(m)_k */
+    double *pe_eff;             /* [F] PE_eff of iteration k (Eq. 4), in [1, M] */
+    uint32_t *n_ex;             /* [F] N_ex used in iteration k */
+    uint32_t *n_ex_next;        /* [F] N_ex that iteration k+1 will use */
+    double *log_z_inc;          /* [F] log p(z_k | z_1:k-1), likelihood-ratio form */
+    uint64_t step;              /* k: iterations completed */
+} pf_estimate_t;
+
+/* Per-PE record, the message each PE sends to the master (Alg. 3, step 9). */
+typedef struct {
+    double log_mass;            /* log W^(m)_k */
+    double xhat[5];             /* x^m_k */
+    float lstar;                /* max_i of the PE's log-weights */
+    uint32_t total_q;           /* sum of the PE's fixed-point weights */
+} pf_pe_record;
+
+/* Create a filter context and initialize its particles (Sec. V: tracking or
+ * information-sharing start).  truth: host [F][5] true initial states.
+ * On success *out owns device memory until pf_destroy. */
+int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out);
+
+/* One full iteration (Alg. 3 steps 1-10; Alg. 2 for RNA) on frame z_k.
+ * d_frame: device float32, [height][width] row-major (patch mode) or
+ * [F][2] observed positions (point mode).  Enqueue only: the frame must stay
+ * valid until the stream has passed this step.  No host synchronization. */
+int pf_step(pf_ctx *c, const float *d_frame);
+
+/* n_steps iterations on consecutive frames d_frames + i * frame_stride
+ * (stride in floats).  Same semantics as n_steps calls of pf_step. */
+int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride);
+
+/* Steps 1-3 of the next iteration alone (Alg. 3; Sec. III-A/C, IV-A/B):
+ * ring, exchange ratio and particle exchange.  If d_src_map (device int64 [N])
+ * is non-NULL it receives the composite source map: slot g is refilled from
+ * slot d_src_map[g] of the previous iteration.  The next pf_step then performs
+ * steps 4-10 with this exchange.  Calling it twice without a pf_step in
+ * between returns PF_ESTATE. */
+int pf_exchange(pf_ctx *c, int64_t *d_src_map);
+
+/* Synchronize the stream and report the last completed iteration (master
+ * estimate, W, PE_eff, N_ex, log-likelihood increment).  Returns PF_ENUMERIC
+ * if any iteration so far produced a NaN log-weight (the flag is sticky). */
+int pf_estimate(pf_ctx *c, pf_estimate_t *out);
+
+/* Free everything the context owns (synchronizes its stream first). */
+void pf_destroy(pf_ctx *c);
+
+/* Static text for a PF_* code. */
+const char *pf_strerror(int code);
+
+/* ------------------------------------------------------------------ debug */
+/* Buffers readable with pf_debug_get (host_dst must hold `bytes` bytes; the
+ * required size is returned through pf_debug_size).  TRACE buffers describe
+ * the last completed iteration and need PF_DEBUG_TRACE. */
+enum {
+    PF_DBG_STATE = 0,      /* float  [5][N] resampled particles */
+    PF_DBG_LOGMASS = 1,    /* double [F][M] log W^(m)_k */
+    PF_DBG_PE_RECORDS = 2, /* pf_pe_record [F][M] */
+    PF_DBG_RING = 3,       /* uint32 [F][M] pred(m) of the last iteration      (TRACE) */
+    PF_DBG_NEX = 4,        /* uint32 [F] N_ex of the last iteration */
+    PF_DBG_SRC = 5,        /* int64  [N] exchange source map                   (TRACE) */
+    PF_DBG_PROP = 6,       /* float  [5][N] propagated particles               (TRACE) */
+    PF_DBG_ELL = 7,        /* float  [N] log-likelihood of each slot           (TRACE) */
+    PF_DBG_Q = 8,          /* uint32 [N] fixed-point weights                   (TRACE) */
+    PF_DBG_ANCESTORS = 9,  /* uint32 [N] ancestor slot within the PE           (TRACE) */
+    PF_DBG_V = 10,         /* uint32 [F][M] systematic offsets                 (TRACE) */
+    PF_DBG_LAMBDA = 11,    /* float  [N] carried log-weight of each slot       (TRACE) */
+    PF_DBG_LINEAGE = 12    /* int32  [N] lineage tags                          (LINEAGE) */
+};
+size_t pf_debug_size(const pf_ctx *c, int which);
+int pf_debug_get(pf_ctx *c, int which, void *host_dst, size_t bytes);
+
+/* Overwrite the particles (host float [5][N]) and the PE log-weights (host
+ * double [F][M], NULL = all zero), and declare `step` iterations completed.
+ * Restores a checkpoint taken with pf_debug_get(STATE / LOGMASS). */
+int pf_debug_set_state(pf_ctx *c, const float *host_state, const double *host_log_mass,
+                       uint64_t step);
+/* Set the lineage tags (host int32 [N]); needs PF_DEBUG_LINEAGE. */
+int pf_debug_set_lineage(pf_ctx *c, const int32_t *host_tags);
+
+/* The device integer stages on host arrays, run synchronously on the current
+ * device with the same device code as pf_step. */
+/* Systematic resampling (Alg. 3, step 7) of n_blocks independent PEs:
+ * q [n_blocks][n_p] fixed-point weights, v [n_blocks] offsets (v < sum q),
+ * anc_out [n_blocks][n_p] ancestors a_j = min{i : n_p C_i > j T + v}. */
+int pf_debug_resample_q(const uint32_t *q, uint32_t n_blocks, uint32_t n_p, const uint32_t *v,
+                        uint32_t *anc_out);
+/* Exchange count (Alg. 3, step 2; Eq. 3 and 4) from integer PE masses p[M]. */
+int pf_debug_nex(const uint32_t *p, uint32_t M, uint32_t n_p, uint32_t mode, float fixed_ratio,
+                 float initial_ratio, float eff_cutoff, int first_iteration, uint32_t *nex_out);
+/* Ring of iteration k of filter f (Alg. 3, step 1): pred_out[M]. */
+int pf_debug_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t mode,
+                  uint32_t *pred_out);
+/* Philox4x32-10 of n counters: ctr [n][4], key [2], out [n][4]. */
+int pf_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t n, uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARNA_H */

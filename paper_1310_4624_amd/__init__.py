@@ -1,0 +1,9 @@
+"""MI355X (gfx950) particle-filter step with RNA / ARNA distributed resampling
+(Demirel et al., arXiv:1310.4624), behind the C interface in include/arna.h.
+
+The HIP library is loaded on first use; importing the package does not touch
+the GPU.
+"""
+from ._native import (PF_INIT_INFOSHARE, PF_INIT_TRACKING, PF_LIK_PATCH, PF_LIK_POINT,  # noqa: F401
+                      PF_MODE_ARNA, PF_MODE_RNA, PF_DEBUG_LINEAGE, PF_DEBUG_TRACE, PFError)
+from .tracker import Tracker, nex, philox, resample_q, ring  # noqa: F401

@@ -1,0 +1,343 @@
+// arna_device.hpp -- device building blocks of the ARNA particle-filter step
+// for gfx950 (wave64).  Everything here is __device__ code used by the kernels
+// in arna.hip, including the debug entry points, so that those exercise the
+// same instructions as pf_step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace arna {
+
+constexpr int kWave = 64;
+
+// Philox stream tags, counter word 3 bits 24..31.  Counter layout:
+// (c0 = index, c1 = step, c2 = filter, c3 = tag << 24 | sub-call), key = seed.
+constexpr uint32_t kTagInit = 1u, kTagRing = 2u, kTagExch = 3u, kTagProp = 4u,
+                   kTagResample = 5u;
+
+struct u4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds; each
+// multiplies words 0 and 2 by the round constants and mixes the high halves
+// with words 1, 3 and the key; the key advances by the Weyl increments.
+__device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// floor(r * n / 2^32), an integer in [0, n).
+__device__ __forceinline__ uint32_t mulshift(uint32_t r, uint32_t n) {
+    return (uint32_t)(((uint64_t)r * n) >> 32);
+}
+
+// (2 (r >> 9) + 1) 2^-24: exact in float32, inside (0, 1).
+__device__ __forceinline__ float unif24(uint32_t r) {
+    return (float)(2u * (r >> 9) + 1u) * 0x1p-24f;
+}
+// (2 b + 1) 2^-19 for an 18-bit field b.
+__device__ __forceinline__ float unif18(uint32_t b) {
+    return (float)(2u * b + 1u) * 0x1p-19f;
+}
+
+// sin / cos of 2 pi t, t in revolutions (native v_sin_f32 / v_cos_f32).
+__device__ __forceinline__ float sin_rev(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ __forceinline__ float cos_rev(float t) { return __builtin_amdgcn_cosf(t); }
+
+// sqrt(-2 ln u) for u in (0, 1), through the native log2.
+__device__ __forceinline__ float bm_radius(float u) {
+    return __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
+}
+
+// Five standard normals from one Philox output: Box-Muller on the top 23 bits
+// of (w0, w1) and (w2, w3), and on two 18-bit fields made of the low 9 bits of
+// the four words (cosine branch).
+__device__ __forceinline__ void five_normals(const u4 r, float e[5]) {
+    const float ra = bm_radius(unif24(r.x));
+    const float ta = unif24(r.y);
+    const float rb = bm_radius(unif24(r.z));
+    const float tb = unif24(r.w);
+    const uint32_t b01 = (r.x & 511u) | ((r.y & 511u) << 9);
+    const uint32_t b23 = (r.z & 511u) | ((r.w & 511u) << 9);
+    const float rc = bm_radius(unif18(b01));
+    e[0] = ra * cos_rev(ta);
+    e[1] = ra * sin_rev(ta);
+    e[2] = rb * cos_rev(tb);
+    e[3] = rb * sin_rev(tb);
+    e[4] = rc * cos_rev(unif18(b23));
+}
+
+struct Dyn {
+    float a;        // sqrt(q / 3): position noise per unit normal
+    float b;        // sqrt(q) sqrt(3) / 2: velocity noise from the same normal
+    float c;        // sqrt(q) / 2: velocity noise from the second normal
+    float sigma_I;  // intensity random walk
+};
+
+// (P): nearly-constant-velocity step, unit time, white-noise acceleration.
+__device__ __forceinline__ void propagate(float s[5], const float e[5], const Dyn &d) {
+    const float x = s[0] + s[2] + d.a * e[0];
+    const float vx = s[2] + (d.b * e[0] + d.c * e[1]);
+    const float y = s[1] + s[3] + d.a * e[2];
+    const float vy = s[3] + (d.b * e[2] + d.c * e[3]);
+    s[0] = x;
+    s[1] = y;
+    s[2] = vx;
+    s[3] = vy;
+    s[4] = s[4] + d.sigma_I * e[4];
+}
+
+struct Lik {
+    const float *img;   // [H][W] (patch) or [F][2] (point)
+    int W, H, half;     // patch half-width
+    float inv2s2;       // 1 / (2 psf_sigma^2)
+    float bg;           // background level
+    float inv_sn2;      // 1 / noise_sigma^2
+};
+
+// (U), patch mode: Gaussian log-likelihood ratio of the spot model against
+// background only over the (2 half + 1)^2 patch centred on the nearest pixel,
+//   l = (I sum g (z - B) - I^2 / 2 sum g^2) / sigma_n^2,
+// with the separable profile g(u, v) = gx(u) gy(v).  Pixels outside the image
+// are skipped (their weights are zero).
+template <int HALF>
+__device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
+    const float cxf = floorf(s[0] + 0.5f);
+    const float cyf = floorf(s[1] + 0.5f);
+    if (!(cxf >= (float)-HALF && cxf <= (float)(L.W - 1 + HALF) && cyf >= (float)-HALF &&
+          cyf <= (float)(L.H - 1 + HALF)))
+        return 0.0f;
+    const int u0 = (int)cxf - HALF, v0 = (int)cyf - HALF;
+    constexpr int P = 2 * HALF + 1;
+    float gx[P];
+    float sx2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const float dx = (float)(u0 + j) - s[0];
+        const bool inx = (unsigned)(u0 + j) < (unsigned)L.W;
+        gx[j] = inx ? __expf(-dx * dx * L.inv2s2) : 0.f;
+        sx2 += gx[j] * gx[j];
+    }
+    // rows three at a time: bounds the loads in flight (and the registers)
+    float acc = 0.f, sy2 = 0.f;
+#pragma unroll 3
+    for (int jv = 0; jv < P; ++jv) {
+        const int vv = v0 + jv;
+        const float dy = (float)vv - s[1];
+        const float gy = ((unsigned)vv < (unsigned)L.H) ? __expf(-dy * dy * L.inv2s2) : 0.f;
+        sy2 += gy * gy;
+        const float *row = L.img + (size_t)min(max(vv, 0), L.H - 1) * L.W;
+        float r = 0.f;
+#pragma unroll
+        for (int ju = 0; ju < P; ++ju) {
+            const int u = min(max(u0 + ju, 0), L.W - 1);
+            const bool in = (unsigned)(u0 + ju) < (unsigned)L.W;
+            const float z = in ? (row[u] - L.bg) : 0.f;
+            r += gx[ju] * z;
+        }
+        acc += gy * r;
+    }
+    const float I = s[4];
+    return (I * acc - 0.5f * I * I * (sx2 * sy2)) * L.inv_sn2;
+}
+
+// (U), point mode: Gaussian position observation of filter f.
+__device__ __forceinline__ float loglik_point(const float s[5], const Lik &L, uint32_t f) {
+    const float dx = s[0] - L.img[2 * f];
+    const float dy = s[1] - L.img[2 * f + 1];
+    return -(dx * dx + dy * dy) * 0.5f * L.inv_sn2;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Block-wide reductions; `scratch` holds at least 8 bytes per wave.  Every
+// thread of the block must call them; all threads get the result.
+__device__ __forceinline__ float block_max(float v, double *scratch) {
+    v = wave_max(v);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) scratch[w] = (double)v;
+    __syncthreads();
+    float r = (float)scratch[0];
+    for (int i = 1; i < nw; ++i) r = fmaxf(r, (float)scratch[i]);
+    return r;
+}
+__device__ __forceinline__ double block_max_d(double v, double *scratch) {
+    v = wave_max_d(v);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) scratch[w] = v;
+    __syncthreads();
+    double r = scratch[0];
+    for (int i = 1; i < nw; ++i) r = fmax(r, scratch[i]);
+    return r;
+}
+// Sum of NV doubles per thread; scratch holds NV doubles per wave.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) scratch[w * NV + c] = v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double r = 0.0;
+        for (int i = 0; i < nw; ++i) r += scratch[i * NV + c];
+        v[c] = r;
+    }
+}
+__device__ __forceinline__ void block_sum_u64(uint64_t (&v)[2], uint64_t *scratch) {
+    v[0] = wave_sum_u64(v[0]);
+    v[1] = wave_sum_u64(v[1]);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        scratch[2 * w] = v[0];
+        scratch[2 * w + 1] = v[1];
+    }
+    __syncthreads();
+    uint64_t a = 0, b = 0;
+    for (int i = 0; i < nw; ++i) {
+        a += scratch[2 * i];
+        b += scratch[2 * i + 1];
+    }
+    v[0] = a;
+    v[1] = b;
+}
+
+// Inclusive prefix sum of c[0..n) in LDS (uint32, exact).  Thread t scans the
+// contiguous chunk [t * per, (t + 1) * per); the chunk totals are scanned
+// across each wave with shuffles and across waves through `wtot`
+// (>= blockDim.x / 64 entries).  Returns the grand total to every thread.
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t *c, int n, int per,
+                                                         uint32_t *wtot) {
+    const int t = threadIdx.x;
+    const int lane = t & (kWave - 1), w = t / kWave, nw = blockDim.x / kWave;
+    const int b = t * per;
+    uint32_t run = 0;
+    for (int i = 0; i < per; ++i)
+        if (b + i < n) run += c[b + i];
+    // inclusive scan of the chunk totals within the wave
+    uint32_t incl = run;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int i = 0; i < nw; ++i) {
+        const uint32_t x = wtot[i];
+        if (i < w) base += x;
+        total += x;
+    }
+    uint32_t acc = base + incl - run;
+    for (int i = 0; i < per; ++i)
+        if (b + i < n) {
+            acc += c[b + i];
+            c[b + i] = acc;
+        }
+    __syncthreads();
+    return total;
+}
+
+// a_j = min { i : n C_i > j T + V } over the inclusive sums C[0..n).
+__device__ __forceinline__ uint32_t systematic_ancestor(const uint32_t *C, uint32_t n,
+                                                        uint64_t target) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)n * C[mid] > target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------- 128-bit integers
+struct u128 {
+    uint64_t hi, lo;
+};
+__device__ __forceinline__ u128 mul64(uint64_t a, uint64_t b) {
+    return {__umul64hi(a, b), a * b};
+}
+// a * s for s < 2^32, assuming no overflow of 128 bits.
+__device__ __forceinline__ u128 mul_small(u128 a, uint32_t s) {
+    return {a.hi * s + __umul64hi(a.lo, s), a.lo * s};
+}
+__device__ __forceinline__ u128 sub128(u128 a, u128 b) {
+    return {a.hi - b.hi - (a.lo < b.lo ? 1u : 0u), a.lo - b.lo};
+}
+__device__ __forceinline__ bool gt128(u128 a, u128 b) {
+    return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
+}
+
+// Exchange count of Alg. 3 step 2 from S = sum P, D = sum P^2 (ARNA), or the
+// fixed rules.  PE_eff = S^2 / D; Eq. 3 gives
+//   N_ex = floor(N_p (M D - S^2) / (2 (M - 1) D)),
+// zero above the cut-off PE_eff > (ppm / 10^6) M, zero for M = 1.
+__device__ __forceinline__ uint32_t exchange_count(uint64_t S, uint64_t D, uint32_t M,
+                                                   uint32_t n_p, uint32_t mode, int first,
+                                                   uint32_t fixed_nex, uint32_t initial_nex,
+                                                   uint32_t cutoff_ppm) {
+    if (M <= 1) return 0;
+    if (mode == 0) return fixed_nex;
+    if (first) return initial_nex;
+    if (D == 0) return n_p / 2;
+    const u128 S2 = mul64(S, S);
+    const u128 MD = mul64((uint64_t)M, D);
+    if (gt128(mul_small(S2, 1000000u), mul_small(MD, cutoff_ppm))) return 0;
+    const u128 num = mul_small(sub128(MD, S2), n_p);
+    const u128 den = mul64(2ull * (M - 1), D);
+    // quotient <= n_p / 2: binary long division over its bits
+    uint32_t qt = 0;
+    for (int bit = 31 - __clz(n_p | 1); bit >= 0; --bit) {
+        const uint32_t cand = qt | (1u << bit);
+        if (!gt128(mul_small(den, cand), num)) qt = cand;
+    }
+    return qt;
+}
+
+}  // namespace arna

@@ -1,0 +1,205 @@
+"""Python face of the C interface: a Tracker object over pf_ctx and the
+device integer stages as functions.  PyTorch supplies device memory (tensor
+data pointers) and the stream; all filter work runs in libarna.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as nat
+
+CONFIG_KEYS = ("n_filters", "n_pe", "n_per_pe", "width", "height", "patch", "mode",
+               "init_mode", "lik_mode", "fixed_ratio", "initial_ratio", "eff_cutoff",
+               "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed")
+
+DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
+                mode=nat.PF_MODE_RNA, init_mode=nat.PF_INIT_TRACKING, lik_mode=nat.PF_LIK_PATCH,
+                fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
+                background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1)
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def make_config(cfg: dict, stream=None, debug: int = 0) -> nat.pf_config:
+    d = dict(DEFAULTS)
+    d.update({k: v for k, v in cfg.items() if k in CONFIG_KEYS})
+    c = nat.pf_config()
+    c.struct_size = ctypes.sizeof(nat.pf_config)
+    for k in CONFIG_KEYS:
+        setattr(c, k, d[k])
+    c.debug = debug
+    c.stream = stream
+    return c
+
+
+def _torch_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous float32")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Tracker:
+    """F independent filters, each of M PEs x N_p particles, on one GPU."""
+
+    def __init__(self, cfg: dict, truth, debug: int = 0, stream=None):
+        d = dict(DEFAULTS)
+        d.update(cfg)
+        self.cfg = d
+        self.F, self.M, self.np_ = d["n_filters"], d["n_pe"], d["n_per_pe"]
+        self.N = self.F * self.M * self.np_
+        self._stream = stream if stream is not None else _torch_stream()
+        self._c = make_config(d, stream=self._stream, debug=debug)
+        t = np.ascontiguousarray(np.asarray(truth, dtype=np.float32).reshape(self.F, 5))
+        h = ctypes.c_void_p()
+        rc = nat.lib().pf_init(ctypes.byref(self._c),
+                               t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h))
+        nat.check(rc, "pf_init")
+        self._h = h
+
+    def frame_numel(self) -> int:
+        """Floats one frame must hold: [H][W] (patch) or [F][2] (point)."""
+        if self.cfg["lik_mode"] == nat.PF_LIK_POINT:
+            return 2 * self.F
+        return self.cfg["width"] * self.cfg["height"]
+
+    # ------------------------------------------------------------ the path
+    def step(self, frame) -> None:
+        if frame.numel() != self.frame_numel():
+            raise ValueError(f"frame has {frame.numel()} values, expected {self.frame_numel()}")
+        nat.check(nat.lib().pf_step(self._h, _dev_ptr(frame, "frame")), "pf_step")
+
+    def run(self, frames, n_steps: int | None = None) -> None:
+        """Consecutive iterations over frames[0], frames[1], ... (first axis)."""
+        n = frames.shape[0] if n_steps is None else n_steps
+        if n > frames.shape[0]:
+            raise ValueError("more steps than frames")
+        stride = int(np.prod(frames.shape[1:]))
+        if stride != self.frame_numel():
+            raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
+        nat.check(nat.lib().pf_run(self._h, _dev_ptr(frames, "frames"), n, stride), "pf_run")
+
+    def exchange(self, src_map=None) -> None:
+        p = None
+        if src_map is not None:
+            import torch
+            if src_map.dtype != torch.int64 or not src_map.is_cuda or src_map.numel() < self.N:
+                raise TypeError("src_map must be a CUDA int64 tensor with N elements")
+            p = ctypes.c_void_p(src_map.data_ptr())
+        nat.check(nat.lib().pf_exchange(self._h, p), "pf_exchange")
+
+    def estimate(self, raise_numeric: bool = True) -> dict:
+        F, M = self.F, self.M
+        out = dict(x_global=np.zeros((F, 5)), x_pe=np.zeros((F, M, 5)),
+                   log_mass_pe=np.zeros((F, M)), log_mass_glob=np.zeros(F), pe_eff=np.zeros(F),
+                   n_ex=np.zeros(F, np.uint32), n_ex_next=np.zeros(F, np.uint32),
+                   log_z_inc=np.zeros(F))
+        e = nat.pf_estimate_t()
+        for k, a in out.items():
+            ct = ctypes.c_uint32 if a.dtype == np.uint32 else ctypes.c_double
+            setattr(e, k, a.ctypes.data_as(ctypes.POINTER(ct)))
+        rc = nat.lib().pf_estimate(self._h, ctypes.byref(e))
+        out["step"] = int(e.step)
+        out["status"] = rc
+        if rc != nat.PF_OK and (rc != nat.PF_ENUMERIC or raise_numeric):
+            nat.check(rc, "pf_estimate")
+        return out
+
+    # ------------------------------------------------------------ debug
+    def debug_get(self, which: str) -> np.ndarray:
+        code = nat.DBG[which]
+        n = nat.lib().pf_debug_size(self._h, code)
+        if n == 0:
+            raise nat.PFError(nat.PF_ESTATE, f"debug buffer {which} not kept (debug flags)")
+        F, M, N = self.F, self.M, self.N
+        shapes = dict(state=((5, N), np.float32), logmass=((F, M), np.float64),
+                      ring=((F, M), np.uint32), nex=((F,), np.uint32), src=((N,), np.int64),
+                      prop=((5, N), np.float32), ell=((N,), np.float32), q=((N,), np.uint32),
+                      ancestors=((N,), np.uint32), v=((F, M), np.uint32),
+                      lam=((N,), np.float32), lineage=((N,), np.int32))
+        if which == "pe_records":
+            a = (nat.pf_pe_record * (F * M))()
+            nat.check(nat.lib().pf_debug_get(self._h, code, ctypes.cast(a, ctypes.c_void_p), n),
+                      "pf_debug_get")
+            return np.array([(r.log_mass, *r.xhat, r.lstar, r.total_q) for r in a]).reshape(F, M, 8)
+        shape, dt = shapes[which]
+        a = np.zeros(shape, dt)
+        assert a.nbytes == n, (which, a.nbytes, n)
+        nat.check(nat.lib().pf_debug_get(self._h, code, _ptr(a), n), "pf_debug_get")
+        return a
+
+    def set_state(self, state, log_mass=None, step: int = 0) -> None:
+        s = np.ascontiguousarray(np.asarray(state, dtype=np.float32).reshape(5, self.N))
+        L = None
+        if log_mass is not None:
+            L = np.ascontiguousarray(np.asarray(log_mass, dtype=np.float64).reshape(-1))
+        nat.check(nat.lib().pf_debug_set_state(self._h, _ptr(s), None if L is None else _ptr(L),
+                                               step), "pf_debug_set_state")
+
+    def set_lineage(self, tags) -> None:
+        t = np.ascontiguousarray(np.asarray(tags, dtype=np.int32).reshape(self.N))
+        nat.check(nat.lib().pf_debug_set_lineage(self._h, _ptr(t)), "pf_debug_set_lineage")
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            nat.lib().pf_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ------------------------------------------------------- device integer stages
+def resample_q(Q, V) -> np.ndarray:
+    """Systematic ancestors on the device: Q [B][n_p] uint32, V [B] uint32."""
+    Q = np.ascontiguousarray(np.atleast_2d(np.asarray(Q, dtype=np.uint32)))
+    V = np.ascontiguousarray(np.atleast_1d(np.asarray(V, dtype=np.uint32)))
+    B, n_p = Q.shape
+    anc = np.zeros((B, n_p), np.uint32)
+    nat.check(nat.lib().pf_debug_resample_q(_ptr(Q), B, n_p, _ptr(V), _ptr(anc)),
+              "pf_debug_resample_q")
+    return anc
+
+
+def nex(P, n_p: int, mode: int = nat.PF_MODE_ARNA, fixed_ratio: float = 0.1,
+        initial_ratio: float = 0.1, cutoff: float = 0.99, first: bool = False) -> int:
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.uint32))
+    out = ctypes.c_uint32()
+    nat.check(nat.lib().pf_debug_nex(_ptr(P), len(P), n_p, mode, fixed_ratio, initial_ratio,
+                                     cutoff, int(first), ctypes.byref(out)), "pf_debug_nex")
+    return int(out.value)
+
+
+def ring(seed: int, f: int, k: int, M: int, mode: int = nat.PF_MODE_ARNA) -> np.ndarray:
+    pred = np.zeros(M, np.uint32)
+    nat.check(nat.lib().pf_debug_ring(seed, f, k, M, mode, _ptr(pred)), "pf_debug_ring")
+    return pred
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.atleast_2d(np.asarray(ctr, dtype=np.uint32)))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros_like(c)
+    nat.check(nat.lib().pf_debug_philox(_ptr(c), _ptr(k), c.shape[0], _ptr(out)),
+              "pf_debug_philox")
+    return out

@@ -1,0 +1,110 @@
+"""Comparison helpers for the GPU-versus-oracle parity tests.
+
+Tolerances follow from the arithmetic of the two sides (FP32 on the GPU, FP64
+in the oracle) started from the same float32 inputs:
+  * a propagated coordinate takes two float32 roundings of values of its own
+    magnitude plus the error of the float32 normals (native log2, sqrt and
+    sin/cos, relative error of a few 1e-7 on |eps| < 6): |dx| <= 2 ulp(x) + 1e-5;
+  * a log-likelihood differs by the effect of those position errors (bounded
+    with the likelihood's gradient over the patch) plus the float32 rounding of
+    its 81-term sums, taken as 2e-6 of the sum of the magnitudes of its terms;
+  * a fixed-point weight Q = floor(exp(u - lstar) Q_max) then moves by at most
+    Q_max w (du + dlstar) + 2.
+Particles whose oracle position lies within the coordinate tolerance of a
+pixel boundary (x + 1/2 an integer) may sit on different patches on the two
+sides; they are not compared element-wise (they are counted and must be rare).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle.oracle as orc
+
+
+def ulp32(x):
+    return np.spacing(np.abs(np.asarray(x, dtype=np.float32))).astype(np.float64)
+
+
+def coord_tol(x, extra=1e-5):
+    return 2.0 * ulp32(np.maximum(np.abs(x), 1.0)) + extra
+
+
+def patch_flip_mask(x, y, tol_x, tol_y):
+    fx = np.mod(np.asarray(x) + 0.5, 1.0)
+    fy = np.mod(np.asarray(y) + 0.5, 1.0)
+    return (fx < tol_x) | (fx > 1 - tol_x) | (fy < tol_y) | (fy > 1 - tol_y)
+
+
+def ell_tolerance(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I):
+    """Per-particle bound on |l_gpu - l_oracle| for patch mode (prop: [5][n])."""
+    x, y, I = prop[0], prop[1], prop[4]
+    half = cfg["patch"] // 2
+    H, W = frame.shape
+    s2 = cfg["psf_sigma"] ** 2
+    sn2 = cfg["noise_sigma"] ** 2
+    B = cfg["background"]
+    cx = np.floor(x + 0.5)
+    cy = np.floor(y + 0.5)
+    gx_abs_sum = np.zeros_like(x)
+    gy_abs_sum = np.zeros_like(x)
+    ggx = np.zeros_like(x)
+    ggy = np.zeros_like(x)
+    sum_gz = np.zeros_like(x)
+    sum_g2 = np.zeros_like(x)
+    sum_abs_gz = np.zeros_like(x)
+    ok = np.isfinite(cx) & np.isfinite(cy) & (np.abs(cx) < 1e8) & (np.abs(cy) < 1e8)
+    cxi = np.where(ok, cx, -10 ** 6).astype(np.int64)
+    cyi = np.where(ok, cy, -10 ** 6).astype(np.int64)
+    for dv in range(-half, half + 1):
+        v = cyi + dv
+        for du in range(-half, half + 1):
+            u = cxi + du
+            inb = (u >= 0) & (u < W) & (v >= 0) & (v < H)
+            z = np.where(inb, frame[np.clip(v, 0, H - 1), np.clip(u, 0, W - 1)], 0.0) - B
+            z = np.where(inb, z, 0.0)
+            ddx = u - x
+            ddy = v - y
+            g = np.where(inb, np.exp(-(ddx * ddx + ddy * ddy) / (2 * s2)), 0.0)
+            dgx = g * np.abs(ddx) / s2
+            dgy = g * np.abs(ddy) / s2
+            gx_abs_sum += dgx * np.abs(z)
+            gy_abs_sum += dgy * np.abs(z)
+            ggx += g * dgx
+            ggy += g * dgy
+            sum_gz += g * z
+            sum_g2 += g * g
+            sum_abs_gz += np.abs(g * z)
+    Gx = (np.abs(I) * gx_abs_sum + I * I * ggx) / sn2
+    Gy = (np.abs(I) * gy_abs_sum + I * I * ggy) / sn2
+    GI = np.abs(sum_gz - I * sum_g2) / sn2
+    mag = (np.abs(I) * sum_abs_gz + 0.5 * I * I * sum_g2) / sn2
+    # the gradient bound is taken at the oracle position; 25% margin for its
+    # change over the (sub-1e-3 px) distance
+    return 1.25 * (Gx * tol_x + Gy * tol_y + GI * tol_I) + 2e-6 * mag + 1e-6
+
+
+def check_ancestors(Qg, Vg, ancg, Qo, Vo, anco, tolQ):
+    """Compare one PE's ancestors.  The GPU ancestors must be valid for the
+    GPU's own fixed-point weights; where they differ from the oracle's, the
+    pointer must lie within the weight tolerance of a cumulative boundary.
+    Returns the number of explained mismatches."""
+    n_p = len(Qg)
+    Cg = np.cumsum(Qg.astype(np.int64))
+    Tg = int(Cg[-1])
+    ptr = np.arange(n_p, dtype=np.int64) * Tg + int(Vg)
+    lo = np.where(ancg == 0, 0, n_p * Cg[np.maximum(ancg.astype(np.int64) - 1, 0)])
+    hi = n_p * Cg[ancg]
+    assert np.all((lo <= ptr) & (ptr < hi)), "GPU ancestors invalid for the GPU's own weights"
+    mism = np.flatnonzero(ancg != anco)
+    if len(mism) == 0:
+        return 0
+    Co = np.cumsum(Qo.astype(np.int64)).astype(np.float64)
+    To = Co[-1]
+    beta = Co / To
+    rho = (np.arange(n_p) * To + Vo) / (n_p * To)
+    eps = 2.0 * float(np.sum(tolQ)) / To + 4.0 / (n_p * To)
+    for j in mism:
+        a, b = sorted((int(ancg[j]), int(anco[j])))
+        d = np.min(np.abs(rho[j] - beta[a:b]))
+        assert d <= eps, (j, int(ancg[j]), int(anco[j]), d, eps)
+    return len(mism)

@@ -1,0 +1,425 @@
+"""GPU path (through the C interface) against the FP64 oracle.
+
+Integer stages are compared bit for bit on identical integer inputs; the float
+stages of one iteration are compared element by element from identical float32
+starting states, within the tolerances derived in tests/helpers.py; multi-step
+runs are compared on what is unique (N_ex, rings) and statistically.
+"""
+import ctypes
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle.oracle as orc
+from paper_1310_4624_amd import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1310_4624_amd  # noqa: F401
+
+
+def pf():
+    import paper_1310_4624_amd as p
+    return p
+
+
+SEED = 0x51D_2013
+
+
+# ------------------------------------------------------------- integer stages
+def test_device_philox_bit_exact():
+    p = pf()
+    rng = np.random.Generator(np.random.PCG64(1))
+    ctr = rng.integers(0, 2 ** 32, (4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0xDEADBEEF, 0x01234567], np.uint32)
+    got = p.philox(ctr, key)
+    for i in range(0, 4096, 97):
+        assert np.array_equal(got[i], orc.philox(ctr[i], key))
+    kat = np.array([[0, 0, 0, 0], [0xFFFFFFFF] * 4], np.uint32)
+    assert list(p.philox(kat[:1], [0, 0])[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert list(p.philox(kat[1:], [0xFFFFFFFF, 0xFFFFFFFF])[0]) == [0x408F276D, 0x41C83B0E,
+                                                                    0xA20BC7C6, 0x6D5451FD]
+
+
+@pytest.mark.parametrize("n_p", [1, 2, 3, 63, 64, 65, 100, 256, 1000, 1024, 1025, 2048, 3333, 4096])
+def test_device_resampling_bit_exact(n_p):
+    p = pf()
+    rng = np.random.Generator(np.random.PCG64(n_p))
+    qm = orc.qmax(n_p)
+    blocks = []
+    for b in range(6):
+        kind = ["mixed", "uniform", "spike", "mixed", "mixed", "mixed"][b]
+        blocks.append(synth.random_weights_q(rng, n_p, qm, kind))
+    Q = np.stack(blocks)
+    T = Q.astype(np.int64).sum(axis=1)
+    V = np.array([rng.integers(0, t) for t in T], np.uint32)
+    V[0] = 0
+    V[1] = T[1] - 1
+    got = p.resample_q(Q, V)
+    for b in range(len(blocks)):
+        assert np.array_equal(got[b], orc.resample(Q[b], int(V[b]))), b
+
+
+def test_device_exchange_count_bit_exact():
+    p = pf()
+    rng = np.random.Generator(np.random.PCG64(2))
+    for trial in range(200):
+        M = int(rng.integers(1, 8193 if trial % 20 == 0 else 400))
+        n_p = int(rng.integers(1, 4097))
+        P = np.floor(np.exp(-rng.exponential(rng.uniform(0.05, 8), M)) * 2 ** 20).astype(np.uint32)
+        P[rng.integers(0, M)] = 1 << 20
+        for mode, first in [(1, False), (1, True), (0, False)]:
+            cut = float(rng.choice([0.99, 0.5, 1.0, 0.0]))
+            a = p.nex(P, n_p, mode=mode, fixed_ratio=0.3, initial_ratio=0.1, cutoff=cut,
+                      first=first)
+            b = orc.nex(P, n_p, mode=mode, fixed_ratio=0.3, initial_ratio=0.1, cutoff=cut,
+                        first=first)
+            assert a == b, (M, n_p, mode, first, cut)
+    P = np.full(100, 1 << 20, np.uint32)
+    P[99] = 0
+    assert p.nex(P, 4096) == orc.nex(P, 4096) == 4096 // 198
+    P[99] = 1
+    assert p.nex(P, 4096) == 0
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 64, 256, 257, 1000])
+def test_device_ring_bit_exact(M):
+    p = pf()
+    for f in [0, 3]:
+        for k in [1, 2, 63, 64, 65, 1000]:
+            got = p.ring(SEED, f, k, M)
+            _, want, _ = orc.ring(SEED, f, k, M)
+            assert np.array_equal(got, want), (M, f, k)
+    assert np.array_equal(p.ring(SEED, 0, 5, M, mode=0), (np.arange(M) - 1) % M)
+
+
+# ------------------------------------------------------- one-step float parity
+def seeded_case(name):
+    rng = np.random.Generator(np.random.PCG64(zlib.crc32(name.encode())))
+    if name == "rna_128_4x256":
+        seq = synth.make_sequence("rna_128_4x256", seed=1003, frames=6)
+        cfg = synth.filter_config("rna_128_4x256", seed=SEED)
+        frame = seq.frames[5]
+        centre = seq.truth[5, :1, :2]
+    elif name == "arna_ragged_2x3x100":
+        cfg = dict(n_filters=2, n_pe=3, n_per_pe=100, width=96, height=80, patch=9,
+                   mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 1)
+        truth = np.array([[[30.3, 40.7, 0, 0, 12.0], [70.6, 20.2, 0, 0, 9.0]]])
+        frame = synth.render(truth[0], 96, 80, 1.5, 5.0, 2.0, rng)
+        centre = truth[0, :, :2]
+    elif name == "arna_1x6x2500":
+        cfg = dict(n_filters=1, n_pe=6, n_per_pe=2500, width=128, height=128, patch=9,
+                   mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 2)
+        truth = np.array([[[64.2, 63.9, 0, 0, 8.0]]])
+        frame = synth.render(truth[0], 128, 128, 1.5, 5.0, 2.0, rng)
+        centre = truth[0, :, :2]
+    elif name == "point_rna_3x5x77":
+        cfg = dict(n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, patch=9,
+                   mode=0, init_mode=0, lik_mode=1, fixed_ratio=0.5, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=1.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 3)
+        centre = rng.uniform(20, 100, (3, 2))
+        frame = (centre + rng.standard_normal((3, 2))).astype(np.float32)
+    else:
+        raise KeyError(name)
+    F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
+    state = synth.random_state(rng, F, M, n_p, cfg["width"], cfg["height"], spread=1.5,
+                               centre=centre, I0=10.0)
+    logmass = rng.normal(0.0, 3.0, (F, M))
+    return cfg, np.asarray(frame, np.float32), state, logmass
+
+
+def run_one_step(cfg, frame, state, logmass, k_done):
+    p = pf()
+    F = cfg["n_filters"]
+    truth = np.zeros((F, 5), np.float32)
+    g = p.Tracker(cfg, truth, debug=p.PF_DEBUG_TRACE)
+    g.set_state(state, logmass, step=k_done)
+    g.step(torch.from_numpy(frame).cuda())
+    est = g.estimate()
+    out = {k: g.debug_get(k) for k in ["ring", "nex", "src", "lam", "prop", "ell", "q",
+                                       "ancestors", "v", "state", "pe_records"]}
+    out["est"] = est
+    g.close()
+    o = orc.Oracle(cfg, truth)
+    o.set_state(state.astype(np.float64), logmass, k_done)
+    tr = o.step(frame)
+    return out, tr
+
+
+@pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
+                                  "point_rna_3x5x77"])
+@pytest.mark.parametrize("k_done", [0, 7])
+def test_one_step_parity(name, k_done):
+    cfg, frame, state, logmass = seeded_case(name)
+    g, tr = run_one_step(cfg, frame, state, logmass, k_done)
+    F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
+    N = F * M * n_p
+    # integer stages of steps 1-3: exact
+    assert np.array_equal(g["ring"], tr["ring_pred"])
+    assert np.array_equal(g["nex"], tr["n_ex"])
+    assert np.array_equal(g["src"], tr["src_map"])
+    assert np.allclose(g["lam"], tr["lambda"], rtol=1e-6, atol=1e-6)
+    # propagated particles
+    tol = np.stack([H.coord_tol(tr["prop"][0]), H.coord_tol(tr["prop"][1]),
+                    H.coord_tol(tr["prop"][2], 2e-5), H.coord_tol(tr["prop"][3], 2e-5),
+                    H.coord_tol(tr["prop"][4])])
+    assert np.all(np.abs(g["prop"] - tr["prop"]) <= tol)
+    # log-likelihoods, except particles on a pixel boundary
+    if cfg["lik_mode"] == 0:
+        tl = np.zeros(N)
+        for f in range(F):
+            sl = slice(f * M * n_p, (f + 1) * M * n_p)
+            tl[sl] = H.ell_tolerance(cfg, frame, tr["prop"][:, sl], tol[0][sl], tol[1][sl],
+                                     tol[4][sl])
+        flip = H.patch_flip_mask(tr["prop"][0], tr["prop"][1], tol[0], tol[1])
+    else:
+        d = np.hypot(tr["prop"][0] - np.repeat(frame[:, 0], M * n_p),
+                     tr["prop"][1] - np.repeat(frame[:, 1], M * n_p))
+        tl = (d * (tol[0] + tol[1]) / cfg["noise_sigma"] ** 2 * 1.25 + 1e-6 * (1 + d * d))
+        flip = np.zeros(N, bool)
+    assert flip.sum() <= max(2, N // 1000)
+    dl = np.abs(g["ell"] - tr["ell"])
+    assert np.all(dl[~flip] <= tl[~flip]), float(np.max(dl[~flip] - tl[~flip]))
+    # fixed-point weights and ancestors, PE by PE
+    qm = orc.qmax(n_p)
+    mism = 0
+    for pe in range(F * M):
+        sl = slice(pe * n_p, (pe + 1) * n_p)
+        if flip[sl].any():
+            continue
+        tlam = 1e-6 * (1 + np.abs(tr["lambda"][sl]))
+        tu = tl[sl] + tlam
+        w = tr["Q"][sl] / qm
+        tq = qm * w * (tu + tu.max()) * 1.01 + 2
+        assert np.all(np.abs(g["q"][sl].astype(np.int64) - tr["Q"][sl].astype(np.int64)) <= tq)
+        f, m = divmod(pe, M)
+        mism += H.check_ancestors(g["q"][sl], g["v"][f, m], g["ancestors"][sl], tr["Q"][sl],
+                                  tr["V"][f, m], tr["anc"][sl], tq)
+    assert mism <= max(2, N // 200)
+    # estimates: per PE and global, 1e-4
+    rec = g["pe_records"]
+    assert np.allclose(rec[:, :, 1:6], tr["xhat_pe"], rtol=0, atol=1e-4)
+    assert np.allclose(g["est"]["x_global"], tr["xhat"], rtol=0, atol=1e-4)
+    assert np.allclose(rec[:, :, 0], tr["L_pe"], rtol=1e-5, atol=1e-3)
+    assert np.allclose(g["est"]["log_z_inc"], tr["log_z"], rtol=1e-5, atol=1e-3)
+    assert np.array_equal(g["est"]["n_ex_next"], tr["n_ex_next"])
+    assert np.allclose(g["est"]["pe_eff"], tr["pe_eff"], rtol=1e-4)
+
+
+def test_exchange_map_export():
+    p = pf()
+    cfg, frame, state, logmass = seeded_case("arna_ragged_2x3x100")
+    g = p.Tracker(cfg, np.zeros((2, 5), np.float32))
+    g.set_state(state, logmass, step=4)
+    src = torch.zeros(g.N, dtype=torch.int64, device="cuda")
+    g.exchange(src)
+    with pytest.raises(p.PFError):
+        g.exchange(None)
+    o = orc.Oracle(cfg, np.zeros((2, 5), np.float32))
+    o.set_state(state.astype(np.float64), logmass, 4)
+    tr = o.step(frame, want={"src_map"})
+    assert np.array_equal(src.cpu().numpy(), tr["src_map"])
+    g.step(torch.from_numpy(frame).cuda())   # steps 4-10 after the exported exchange
+    g.close()
+
+
+# ------------------------------------------------------------- multi-step runs
+def test_rna_small_workload_end_to_end():
+    p = pf()
+    seq = synth.make_sequence("rna_128_4x256", seed=1000)
+    cfg = synth.filter_config("rna_128_4x256", seed=3)
+    truth0 = seq.initial_truth()[:1]
+    g = p.Tracker(cfg, truth0, debug=p.PF_DEBUG_TRACE)
+    o = orc.Oracle(cfg, truth0)
+    frames = torch.from_numpy(seq.frames).cuda()
+    eg, eo = [], []
+    for k in range(1, seq.frames.shape[0] + 1):
+        g.step(frames[k - 1])
+        est = g.estimate()
+        tr = o.step(seq.frames[k - 1], want={"xhat", "n_ex", "ring_pred"})
+        assert est["step"] == k
+        assert int(est["n_ex"][0]) == int(tr["n_ex"][0]) == 25
+        assert np.array_equal(g.debug_get("ring"), tr["ring_pred"])
+        if k == 1:
+            assert np.allclose(est["x_global"], tr["xhat"], atol=1e-4, rtol=0)
+        assert np.abs(est["x_global"][0, :2] - tr["xhat"][0, :2]).max() < 0.15
+        eg.append(est["x_global"][0, :2] - seq.truth[k, 0, :2])
+        eo.append(tr["xhat"][0, :2] - seq.truth[k, 0, :2])
+    g.close()
+    assert np.sqrt(np.mean(np.square(eg))) < 0.5
+    assert np.sqrt(np.mean(np.square(eo))) < 0.5
+
+
+def test_determinism_and_resume_bitwise():
+    p = pf()
+    seq = synth.make_sequence("rna_128_4x256", seed=1001, frames=8)
+    cfg = synth.filter_config("rna_128_4x256", seed=11, mode=1, n_pe=8, n_per_pe=300)
+    truth0 = seq.initial_truth()[:1]
+    frames = torch.from_numpy(seq.frames).cuda()
+
+    def run(n, tr=None):
+        t = tr or p.Tracker(cfg, truth0)
+        t.run(frames[:n])
+        return t
+
+    a = run(8)
+    b = run(8)
+    sa, sb = a.debug_get("state"), b.debug_get("state")
+    assert np.array_equal(sa, sb)
+    assert np.array_equal(a.debug_get("pe_records"), b.debug_get("pe_records"))
+    c = run(4)
+    st, L = c.debug_get("state"), c.debug_get("logmass")
+    c.close()
+    d = p.Tracker(cfg, truth0)
+    d.set_state(st, L, step=4)
+    d.run(frames[4:8])
+    assert np.array_equal(d.debug_get("state"), sa)
+    assert np.array_equal(d.debug_get("logmass"), a.debug_get("logmass"))
+    for t in (a, b, d):
+        t.close()
+
+
+def test_infoshare_init_parity():
+    p = pf()
+    cfg = synth.filter_config("arna_infoshare_512_256x4096", n_pe=16, n_per_pe=512, seed=5)
+    truth = np.array([[200.3, 300.6, 1.0, -0.5, 8.0]], np.float32)
+    g = p.Tracker(cfg, truth)
+    st = g.debug_get("state")
+    g.close()
+    o = orc.Oracle(cfg, truth)
+    so, L, k = o.get_state()
+    assert k == 0 and np.all(L == 0)
+    for c in range(5):
+        assert np.all(np.abs(st[c] - so[c]) <= H.coord_tol(so[c]))
+
+
+def test_edge_single_pe_single_particle_and_full_exchange():
+    p = pf()
+    rng = np.random.Generator(np.random.PCG64(9))
+    frame = synth.render(np.array([[20.0, 20.0, 0, 0, 10.0]]), 40, 40, 1.5, 5.0, 2.0, rng)
+    ft = torch.from_numpy(frame).cuda()
+    for over in [dict(n_pe=1, n_per_pe=64, mode=1), dict(n_pe=3, n_per_pe=1, mode=0,
+                                                        fixed_ratio=1.0),
+                 dict(n_pe=4, n_per_pe=50, mode=0, fixed_ratio=1.0)]:
+        cfg = dict(n_filters=1, width=40, height=40, patch=9, init_mode=0, lik_mode=0,
+                   initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5, background=5.0,
+                   noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=21, fixed_ratio=0.1)
+        cfg.update(over)
+        truth = np.array([[20.0, 20.0, 0.0, 0.0, 10.0]], np.float32)
+        g = p.Tracker(cfg, truth, debug=p.PF_DEBUG_TRACE)
+        o = orc.Oracle(cfg, truth)
+        g.step(ft)
+        est = g.estimate()
+        tr = o.step(frame)
+        assert np.array_equal(g.debug_get("src"), tr["src_map"])
+        assert int(est["n_ex"][0]) == int(tr["n_ex"][0])
+        assert np.allclose(est["x_global"], tr["xhat"], atol=1e-4, rtol=0)
+        g.close()
+
+
+def test_nan_pixel_sets_sticky_numeric_error():
+    p = pf()
+    frame = np.full((40, 40), 5.0, np.float32)
+    frame[20, 20] = np.nan
+    cfg = dict(n_filters=1, n_pe=2, n_per_pe=64, width=40, height=40, seed=2)
+    g = p.Tracker(cfg, np.array([[20.0, 20.0, 0, 0, 10.0]], np.float32))
+    g.step(torch.from_numpy(frame).cuda())
+    with pytest.raises(p.PFError) as ei:
+        g.estimate()
+    assert ei.value.code == -4
+    g.step(torch.from_numpy(np.full((40, 40), 5.0, np.float32)).cuda())
+    assert g.estimate(raise_numeric=False)["status"] == -4   # sticky
+    g.close()
+
+
+def test_dead_pe_gets_no_mass():
+    p = pf()
+    cfg = dict(n_filters=1, n_pe=4, n_per_pe=64, width=40, height=40, seed=2, mode=0,
+               fixed_ratio=0.0)
+    rng = np.random.Generator(np.random.PCG64(4))
+    state = synth.random_state(rng, 1, 4, 64, 40, 40, spread=1.0, centre=[[20, 20]])
+    L = np.array([[0.0, -np.inf, 0.0, 0.0]])
+    g = p.Tracker(cfg, np.zeros((1, 5), np.float32))
+    g.set_state(state, L, step=3)
+    frame = synth.render(np.array([[20.0, 20.0, 0, 0, 10.0]]), 40, 40, 1.5, 5.0, 2.0, rng)
+    g.step(torch.from_numpy(frame).cuda())
+    est = g.estimate()
+    o = orc.Oracle(cfg, np.zeros((1, 5), np.float32))
+    o.set_state(state.astype(np.float64), L, 3)
+    tr = o.step(frame, want={"L_pe", "xhat", "pe_eff"})
+    assert est["log_mass_pe"][0, 1] == -np.inf and tr["L_pe"][0, 1] == -np.inf
+    assert np.allclose(est["x_global"], tr["xhat"], atol=1e-4, rtol=0)
+    assert est["pe_eff"][0] <= 3.0 + 1e-9
+    g.close()
+
+
+# --------------------------------------------------------- information spread
+def lineage_run(mode, M, n_p, steps):
+    p = pf()
+    cfg = dict(n_filters=1, n_pe=M, n_per_pe=n_p, width=64, height=64, mode=mode,
+               lik_mode=1, fixed_ratio=0.5, initial_ratio=0.5, eff_cutoff=1.0,
+               noise_sigma=3.0, seed=4242)
+    g = p.Tracker(cfg, np.array([[32.0, 32.0, 0.0, 0.0, 5.0]], np.float32),
+                  debug=p.PF_DEBUG_LINEAGE | p.PF_DEBUG_TRACE)
+    g.set_lineage(np.repeat(np.arange(M), n_p))
+    z = torch.tensor([[32.0, 32.0]], dtype=torch.float32, device="cuda")
+    infected, rings = [{0}], []
+    for k in range(steps):
+        g.step(z)
+        tags = g.debug_get("lineage").reshape(M, n_p)
+        infected.append({m for m in range(M) if np.any(tags[m] == 0)})
+        rings.append(g.debug_get("ring")[0].copy())
+    g.close()
+    return infected, rings
+
+
+def test_gpu_fixed_ring_confines_lineage():
+    infected, _ = lineage_run(0, 12, 32, 8)
+    for k, inf in enumerate(infected):
+        assert inf <= set(range(k + 1))
+
+
+def test_gpu_random_ring_infection_at_most_doubles():
+    infected, rings = lineage_run(1, 32, 32, 8)
+    for k in range(1, len(infected)):
+        pred = rings[k - 1]
+        reach = infected[k - 1] | {m for m in range(32) if int(pred[m]) in infected[k - 1]}
+        assert infected[k] <= reach
+
+
+# ---------------------------------------------- Philox against rocRAND (P8)
+def test_oracle_philox_matches_rocrand_host_generator():
+    """rocRAND's PHILOX4_32_10 run as a black box (its host generator needs a
+    HIP device to allocate, so this runs on the GPU machine)."""
+    import os
+    path = "/opt/rocm/lib/librocrand.so"
+    lib = ctypes.CDLL(path if os.path.exists(path) else "librocrand.so")
+    gen = ctypes.c_void_p()
+    if lib.rocrand_create_generator_host_blocking(ctypes.byref(gen), 404) != 0:
+        pytest.skip("rocRAND host generator unavailable")
+    seed = 0x0123456789ABCDEF
+    assert lib.rocrand_set_seed(gen, ctypes.c_ulonglong(seed)) == 0
+    n = 4096
+    out = np.zeros(n, np.uint32)
+    st = lib.rocrand_generate(gen, out.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(n))
+    lib.rocrand_destroy_generator(gen)
+    assert st == 0
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    blocks = {tuple(orc.philox([i, 0, 0, 0], key)) for i in range(n // 4)}
+    got = {tuple(out[4 * i:4 * i + 4]) for i in range(n // 4)}
+    assert got == blocks
