@@ -61,7 +61,7 @@ __device__ __forceinline__ float cos_rev(float t) { return __builtin_amdgcn_cosf
 
 // sqrt(-2 ln u) for u in (0, 1), through the native log2.
 __device__ __forceinline__ float bm_radius(float u) {
-    return __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
+    return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
 }
 
 // Five standard normals from one Philox output: Box-Muller on the top 23 bits
@@ -104,56 +104,135 @@ __device__ __forceinline__ void propagate(float s[5], const float e[5], const Dy
 
 struct Lik {
     const float *img;   // [H][W] (patch) or [F][2] (point)
-    int W, H, half;     // patch half-width
-    float inv2s2;       // 1 / (2 psf_sigma^2)
+    int W, H;
+    float inv2s2;       // c = 1 / (2 psf_sigma^2)
+    float k2;           // exp(-2 c), the step of the profile recurrence
     float bg;           // background level
     float inv_sn2;      // 1 / noise_sigma^2
 };
 
 // (U), patch mode: Gaussian log-likelihood ratio of the spot model against
-// background only over the (2 half + 1)^2 patch centred on the nearest pixel,
+// background only over the (2 HALF + 1)^2 patch centred on the nearest pixel,
 //   l = (I sum g (z - B) - I^2 / 2 sum g^2) / sigma_n^2,
 // with the separable profile g(u, v) = gx(u) gy(v).  Pixels outside the image
-// are skipped (their weights are zero).
+// are skipped (their weights are zero).  The patch position is decided first
+// (patch_origin); the sums then read the pixels from one of three sources.
 template <int HALF>
-__device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
-    const float cxf = floorf(s[0] + 0.5f);
-    const float cyf = floorf(s[1] + 0.5f);
-    if (!(cxf >= (float)-HALF && cxf <= (float)(L.W - 1 + HALF) && cyf >= (float)-HALF &&
-          cyf <= (float)(L.H - 1 + HALF)))
-        return 0.0f;
-    const int u0 = (int)cxf - HALF, v0 = (int)cyf - HALF;
+__device__ __forceinline__ bool patch_origin(float x, float y, int W, int H, int &u0, int &v0) {
+    const float cxf = floorf(x + 0.5f);
+    const float cyf = floorf(y + 0.5f);
+    if (!(cxf >= (float)-HALF && cxf <= (float)(W - 1 + HALF) && cyf >= (float)-HALF &&
+          cyf <= (float)(H - 1 + HALF)))
+        return false;
+    u0 = (int)cxf - HALF;
+    v0 = (int)cyf - HALF;
+    return true;
+}
+
+enum PixelSource { kFromTile = 0, kFromImage = 1, kFromImageBorder = 2, kFromTileInside = 3 };
+
+// SRC = kFromTile: `pix` points at (z - B) of the patch's first pixel in an
+//   LDS tile of row pitch `pitch`, already zero outside the image;
+// SRC = kFromTileInside: the same, for a tile that lies inside the image;
+// SRC = kFromImage: `pix` points at the first pixel in the frame, the whole
+//   patch lies inside the image (row pitch = W);
+// SRC = kFromImageBorder: `pix` is the frame; every read is clamped and masked.
+// The P profile values exp(-(u0 + j - x)^2 c), j = 0..2 HALF, by a recurrence
+// outward from the centre pixel u0 + HALF (|d| <= 1/2): with d_j = u0 + j - x,
+//   g_{j+1} = g_j r_j,  r_j = exp(-(2 d_j + 1) c),  r_{j+1} = r_j exp(-2 c),
+// and symmetrically downward; every factor is <= 1, so values only shrink and
+// underflow exactly where the profile itself does.  3 exponentials per axis.
+template <int HALF>
+__device__ __forceinline__ void profile(float d_centre, float c, float k2, float (&g)[2 * HALF + 1]) {
+    g[HALF] = __expf(-d_centre * d_centre * c);
+    float up = __expf(-(2.f * d_centre + 1.f) * c);
+    float dn = __expf((2.f * d_centre - 1.f) * c);
+#pragma unroll
+    for (int j = 1; j <= HALF; ++j) {
+        g[HALF + j] = g[HALF + j - 1] * up;
+        g[HALF - j] = g[HALF - j + 1] * dn;
+        up *= k2;
+        dn *= k2;
+    }
+}
+
+// SRC = kFromTile: `pix` points at (z - B) of the patch's first pixel in an
+//   LDS tile of row pitch `pitch`, already zero outside the image;
+// SRC = kFromImage: `pix` points at the first pixel in the frame, the whole
+//   patch lies inside the image (row pitch = W);
+// SRC = kFromImageBorder: `pix` is the frame; every read is clamped and masked.
+template <int HALF, int SRC>
+__device__ __forceinline__ float patch_loglik(const float s[5], int u0, int v0, const float *pix,
+                                              int pitch, const Lik &L) {
     constexpr int P = 2 * HALF + 1;
-    float gx[P];
-    float sx2 = 0.f;
+    float gx[P], gy[P];
+    profile<HALF>((float)(u0 + HALF) - s[0], L.inv2s2, L.k2, gx);
+    profile<HALF>((float)(v0 + HALF) - s[1], L.inv2s2, L.k2, gy);
+    // pixels outside the image carry no weight (only patches at the border)
+    constexpr bool inside = SRC == kFromImage || SRC == kFromTileInside;
+    if (!inside && (u0 < 0 || v0 < 0 || u0 + P > L.W || v0 + P > L.H)) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if ((unsigned)(u0 + j) >= (unsigned)L.W) gx[j] = 0.f;
+            if ((unsigned)(v0 + j) >= (unsigned)L.H) gy[j] = 0.f;
+        }
+    }
+    float sx2 = 0.f, sy2 = 0.f;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const float dx = (float)(u0 + j) - s[0];
-        const bool inx = (unsigned)(u0 + j) < (unsigned)L.W;
-        gx[j] = inx ? __expf(-dx * dx * L.inv2s2) : 0.f;
         sx2 += gx[j] * gx[j];
+        sy2 += gy[j] * gy[j];
     }
-    // rows three at a time: bounds the loads in flight (and the registers)
-    float acc = 0.f, sy2 = 0.f;
+    float acc = 0.f;
+    if (SRC == kFromTile || SRC == kFromTileInside) {
+#pragma unroll
+        for (int jv = 0; jv < P; ++jv) {
+            const float *row = pix + jv * pitch;
+            float r = 0.f;
+#pragma unroll
+            for (int ju = 0; ju < P; ++ju) r += gx[ju] * row[ju];
+            acc += gy[jv] * r;
+        }
+        const float I = s[4];
+        return (I * acc - 0.5f * I * I * (sx2 * sy2)) * L.inv_sn2;
+    }
+    // frame rows three at a time: bounds the loads in flight (and the registers)
 #pragma unroll 3
     for (int jv = 0; jv < P; ++jv) {
-        const int vv = v0 + jv;
-        const float dy = (float)vv - s[1];
-        const float gy = ((unsigned)vv < (unsigned)L.H) ? __expf(-dy * dy * L.inv2s2) : 0.f;
-        sy2 += gy * gy;
-        const float *row = L.img + (size_t)min(max(vv, 0), L.H - 1) * L.W;
         float r = 0.f;
+        if (SRC == kFromTile) {
+            const float *row = pix + jv * pitch;
 #pragma unroll
-        for (int ju = 0; ju < P; ++ju) {
-            const int u = min(max(u0 + ju, 0), L.W - 1);
-            const bool in = (unsigned)(u0 + ju) < (unsigned)L.W;
-            const float z = in ? (row[u] - L.bg) : 0.f;
-            r += gx[ju] * z;
+            for (int ju = 0; ju < P; ++ju) r += gx[ju] * row[ju];
+        } else if (SRC == kFromImage) {
+            const float *row = pix + (size_t)jv * L.W;
+#pragma unroll
+            for (int ju = 0; ju < P; ++ju) r += gx[ju] * (row[ju] - L.bg);
+        } else {
+            const int vv = v0 + jv;
+            const float *row = pix + (size_t)min(max(vv, 0), L.H - 1) * L.W;
+#pragma unroll
+            for (int ju = 0; ju < P; ++ju) {
+                const int u = min(max(u0 + ju, 0), L.W - 1);
+                const bool in = (unsigned)(u0 + ju) < (unsigned)L.W;
+                r += gx[ju] * (in ? (row[u] - L.bg) : 0.f);
+            }
         }
-        acc += gy * r;
+        acc += gy[jv] * r;
     }
     const float I = s[4];
     return (I * acc - 0.5f * I * I * (sx2 * sy2)) * L.inv_sn2;
+}
+
+// Patch likelihood straight from the frame (no LDS tile).
+template <int HALF>
+__device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
+    int u0, v0;
+    if (!patch_origin<HALF>(s[0], s[1], L.W, L.H, u0, v0)) return 0.0f;
+    constexpr int P = 2 * HALF + 1;
+    if (u0 >= 0 && v0 >= 0 && u0 + P <= L.W && v0 + P <= L.H)
+        return patch_loglik<HALF, kFromImage>(s, u0, v0, L.img + (size_t)v0 * L.W + u0, 0, L);
+    return patch_loglik<HALF, kFromImageBorder>(s, u0, v0, L.img, 0, L);
 }
 
 // (U), point mode: Gaussian position observation of filter f.
@@ -161,6 +240,71 @@ __device__ __forceinline__ float loglik_point(const float s[5], const Lik &L, ui
     const float dx = s[0] - L.img[2 * f];
     const float dy = s[1] - L.img[2 * f + 1];
     return -(dx * dx + dy * dy) * 0.5f * L.inv_sn2;
+}
+
+// ------------------------------------------------------------- DPP wave ops
+// gfx9 DPP controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.  Lanes without a source take `old` (the identity).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp(uint32_t v, uint32_t ident) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive scan over the 64 lanes (Hillis-Steele within rows of 16, then
+// row broadcasts).  OP combines two values given as bits.
+template <class OP>
+__device__ __forceinline__ uint32_t wave_scan_bits(uint32_t v, uint32_t ident, OP op) {
+    v = op(v, dpp<0x111, 0xF>(v, ident));
+    v = op(v, dpp<0x112, 0xF>(v, ident));
+    v = op(v, dpp<0x114, 0xF>(v, ident));
+    v = op(v, dpp<0x118, 0xF>(v, ident));
+    v = op(v, dpp<0x142, 0xA>(v, ident));
+    v = op(v, dpp<0x143, 0xC>(v, ident));
+    return v;
+}
+__device__ __forceinline__ uint32_t lane63(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    return wave_scan_bits(v, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
+__device__ __forceinline__ float wave_max_f32(float v) {
+    const uint32_t r = wave_scan_bits(__float_as_uint(v), 0xFF800000u, [](uint32_t a, uint32_t b) {
+        return __float_as_uint(fmaxf(__uint_as_float(a), __uint_as_float(b)));
+    });
+    return __uint_as_float(lane63(r));
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+    const uint32_t r = wave_scan_bits((uint32_t)v, 0x7FFFFFFFu, [](uint32_t a, uint32_t b) {
+        return (uint32_t)min((int)a, (int)b);
+    });
+    return (int)lane63(r);
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+    const uint32_t r = wave_scan_bits((uint32_t)v, 0x80000000u, [](uint32_t a, uint32_t b) {
+        return (uint32_t)max((int)a, (int)b);
+    });
+    return (int)lane63(r);
+}
+// Sum of a double over the wave (every lane gets it), in a fixed order.
+__device__ __forceinline__ double wave_total_f64(double v) {
+#define ARNA_DPP_F64(CTRL, ROWS)                                                      \
+    {                                                                                \
+        const uint64_t b = __double_as_longlong(v);                                  \
+        const uint32_t lo = dpp<CTRL, ROWS>((uint32_t)b, 0u);                         \
+        const uint32_t hi = dpp<CTRL, ROWS>((uint32_t)(b >> 32), 0u);                 \
+        v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));           \
+    }
+    ARNA_DPP_F64(0x111, 0xF)
+    ARNA_DPP_F64(0x112, 0xF)
+    ARNA_DPP_F64(0x114, 0xF)
+    ARNA_DPP_F64(0x118, 0xF)
+    ARNA_DPP_F64(0x142, 0xA)
+    ARNA_DPP_F64(0x143, 0xC)
+#undef ARNA_DPP_F64
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = lane63((uint32_t)b), hi = lane63((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // ---------------------------------------------------------------- reductions
@@ -282,18 +426,23 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t *c, int n, int
     return total;
 }
 
-// a_j = min { i : n C_i > j T + V } over the inclusive sums C[0..n).
+// a_j = min { i : n C_i > j T + V } over the inclusive sums C[0..n).  For
+// integer C this is min { i : C_i > tau } with tau = floor((j T + V) / n), a
+// 32-bit lower bound found by binary lifting (C[n-1] = T > tau always).
 __device__ __forceinline__ uint32_t systematic_ancestor(const uint32_t *C, uint32_t n,
-                                                        uint64_t target) {
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if ((uint64_t)n * C[mid] > target)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
+                                                        uint32_t tau, uint32_t top) {
+    uint32_t pos = 0;   // number of leading entries <= tau
+    for (uint32_t step = top; step > 0; step >>= 1)
+        if (pos + step <= n && C[pos + step - 1] <= tau) pos += step;
+    return pos;
+}
+// floor(num / n) for num < 2^53, n >= 1, through a double reciprocal and one
+// integer correction either way.
+__device__ __forceinline__ uint32_t div_floor(uint64_t num, uint32_t n, double inv_n) {
+    uint64_t q = (uint64_t)((double)num * inv_n);
+    if (q * n > num) --q;
+    else if ((q + 1) * n <= num) ++q;
+    return (uint32_t)q;
 }
 
 // ------------------------------------------------------- 128-bit integers
