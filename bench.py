@@ -7,10 +7,16 @@ resident in HBM.  Prints one JSON line.
 
 Default workload: the ARNA tracking configuration, 4 filters x 64 PEs x 4096
 particles (2^20 particles), 512 x 512 frames with 4 spots of SNR 2..6.
+
+Timing: after the warm-up, one pf_run of K steps is bracketed by two HIP
+events on the stream the kernels run on (the metric).  A second region of
+steps, each bracketed by events that the library records on the same stream,
+gives the step kernel's average duration for the roofline entry.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,50 +30,79 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s, full ARNA SIR step at 2^20 particles; fwd+bwd/fwd cost ratio"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per particle-step: read the float32 state (5 x 4 B),
-# write the resampled state (5 x 4 B), and the frame (H W 4 B) shared by the
-# N particles; the exchange is a read-index remap and moves no extra bytes.
+# write the resampled state (5 x 4 B); plus the frame (H W 4 B) once per step,
+# shared by all particles.  The exchange is a read-index remap and moves no
+# extra bytes.
 STATE_BYTES = 40.0
+# the device code (kernels and their helpers); host-side changes keep the record
+KERNEL_SOURCES = ["paper_1310_4624_amd/csrc/arna_kernels.hpp",
+                  "paper_1310_4624_amd/csrc/arna_device.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
 
 
 def algorithmic_bytes(n_particles: int, width: int, height: int) -> float:
     return STATE_BYTES * n_particles + 4.0 * width * height
 
 
-def gpu_leg(workload: str, steps: int, warmup: int, seed: int):
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per k_step launch from the committed counter summary, or None
+    when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int):
     import torch
     from paper_1310_4624_amd import Tracker, synth
 
     cfg = synth.filter_config(workload, seed=seed)
-    seq = synth.make_sequence(workload, seed=1000, frames=warmup + steps)
+    n_frames = max(warmup + steps + probe, synth.WORKLOADS[workload]["seq"]["frames"])
+    seq = synth.make_sequence(workload, seed=1000, frames=n_frames)
     F = cfg["n_filters"]
-    truth0 = seq.initial_truth()[:F]
     torch.cuda.set_device(0)
-    frames = torch.from_numpy(seq.frames).cuda()
+    frames = torch.from_numpy(seq.frames[:warmup + steps + probe]).cuda()
     stream = torch.cuda.current_stream()
-    tr = Tracker(cfg, truth0)
+    tr = Tracker(cfg, seq.initial_truth()[:F])
     if warmup:
         tr.run(frames[:warmup])
     torch.cuda.synchronize()
-    # per-step HIP events on the stream the kernels are launched on
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+
+    # timed region: K steps in one call, two events
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(steps):
-        tr.step(frames[warmup + i])
-        ev[i + 1].record(stream)
+    e0.record(stream)
+    tr.run(frames[warmup:warmup + steps])
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = ev[0].elapsed_time(ev[steps])
-    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    total_ms = e0.elapsed_time(e1)
+
+    # kernel-duration region: the library records a pair of HIP events around
+    # each launch on the same stream (no host round trip in between)
+    per = tr.run_timed(frames[warmup + steps:warmup + steps + probe]).astype(np.float64)
+    ks = warmup + steps + 1 + np.arange(probe)
+    # iterations k = 1, 65, 129, ... also build the next 64 rings (ARNA)
+    ring = (ks - 1) % 64 == 0 if cfg["mode"] == 1 else np.zeros(probe, bool)
+    step_ms = float(per[~ring].mean()) if (~ring).any() else float(per.mean())
     est = tr.estimate()
     tr.close()
-    # iterations k = 1, 65, 129, ... also build the next 64 rings (ARNA)
-    ks = warmup + 1 + np.arange(steps)
-    ring_steps = (ks - 1) % 64 == 0 if cfg["mode"] == 1 else np.zeros(steps, bool)
-    step_ms = float(per[~ring_steps].mean()) if (~ring_steps).any() else float(per.mean())
     return dict(cfg=cfg, seq=seq, total_ms=total_ms, wall_s=wall, step_kernel_ms=step_ms,
-                per_step_ms=per.tolist(), pe_eff=est["pe_eff"].tolist(),
-                n_ex=est["n_ex"].tolist())
+                pe_eff=est["pe_eff"].tolist(), n_ex=est["n_ex"].tolist())
 
 
 def cpu_leg(workload: str, seed: int, budget_s: float, seq):
@@ -88,26 +123,42 @@ def cpu_leg(workload: str, seed: int, budget_s: float, seq):
         done += 1
     return dict(value=N * done / t, unit="particle-steps/s", cores=orc.num_threads(),
                 kind="oracle",
-                sample=f"{workload}: first {done} iteration(s) of the same sequence, "
-                       f"{N} particles, FP64, {t:.1f} s")
+                sample=f"{workload}: iterations 1-{done} of the same sequence, {N} particles, "
+                       f"FP64, {t:.1f} s")
 
 
 def main():
+    from paper_1310_4624_amd import synth
+
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
+    ap.add_argument("--probe", type=int, default=20, help="single steps timed for the roofline")
+    ap.add_argument("--workload", default="arna_tracking_512_4x64x4096",
+                    choices=sorted(synth.WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
               "multi-GPU sharding of the path is a design note, not code", file=sys.stderr)
         sys.exit(2)
 
-    g = gpu_leg(args.workload, args.steps, args.warmup, args.seed)
+    g = gpu_leg(args.workload, args.steps, args.warmup, args.seed, args.probe)
     cfg = g["cfg"]
     N = cfg["n_filters"] * cfg["n_pe"] * cfg["n_per_pe"]
     ms = g["total_ms"] / args.steps
@@ -133,9 +184,12 @@ def main():
                    "mode": "ARNA" if cfg["mode"] == 1 else "RNA",
                    "parallelism": "one PE per workgroup, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload),
                      "kernel": "k_step", "kernel_ms": g["step_kernel_ms"],
-                     "bytes_per_launch": bytes_launch},
+                     "bytes_per_launch": bytes_launch, "kernel_sha": kernel_sha()},
+        "final_pe_eff": g["pe_eff"],
+        "final_n_ex": g["n_ex"],
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_leg(args.workload, args.seed, args.cpu_budget, g["seq"])

@@ -120,6 +120,13 @@ int pf_step(pf_ctx *c, const float *d_frame);
  * (stride in floats).  Same semantics as n_steps calls of pf_step. */
 int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride);
 
+/* pf_run that also times every iteration with a pair of HIP events recorded
+ * on the context's stream around its launches, then synchronizes the stream.
+ * host_ms_out (host float [n_steps]) receives each iteration's duration in
+ * milliseconds (the ring table build of every 64th iteration included). */
+int pf_run_timed(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
+                 float *host_ms_out);
+
 /* Steps 1-3 of the next iteration alone (Alg. 3; Sec. III-A/C, IV-A/B):
  * ring, exchange ratio and particle exchange.  If d_src_map (device int64 [N])
  * is non-NULL it receives the composite source map: slot g is refilled from

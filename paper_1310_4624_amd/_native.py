@@ -76,6 +76,8 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_void_p)]),
     "pf_step": (ctypes.c_int, [_P, _P]),
     "pf_run": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64]),
+    "pf_run_timed": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64,
+                                    ctypes.POINTER(ctypes.c_float)]),
     "pf_exchange": (ctypes.c_int, [_P, _P]),
     "pf_estimate": (ctypes.c_int, [_P, ctypes.POINTER(pf_estimate_t)]),
     "pf_destroy": (None, [_P]),

@@ -8,7 +8,8 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "arna.hip")
-DEPS = [SRC, os.path.join(PKG, "csrc", "arna_device.hpp"), os.path.join(ROOT, "include", "arna.h")]
+DEPS = [SRC, os.path.join(PKG, "csrc", "arna_device.hpp"), os.path.join(PKG, "csrc", "arna_kernels.hpp"),
+        os.path.join(ROOT, "include", "arna.h")]
 LIB = os.path.join(PKG, "libarna.so")
 ARCH = "gfx950"
 

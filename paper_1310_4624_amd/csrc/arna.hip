@@ -24,623 +24,11 @@
 
 #include "arna.h"
 #include "arna_device.hpp"
+#include "arna_kernels.hpp"
 
 using namespace arna;
 
 namespace {
-
-constexpr uint32_t kRingSteps = 64;     // iterations per ring-table batch
-constexpr int kRedDoubles = 128;        // LDS reduction scratch (>= 16 waves x 8)
-
-struct EstDev {                         // written by k_global, one per filter
-    double xhat[5];
-    double log_mass_glob;
-    double pe_eff;
-    double log_z;
-    uint32_t n_ex_next;
-    uint32_t pad;
-};
-
-// Buffers kept only in debug modes (one device copy per context).
-struct DebugBufs {
-    // trace of the last iteration (PF_DEBUG_TRACE), else NULL
-    uint32_t *t_pred, *t_q, *t_anc, *t_v;
-    int64_t *t_src;
-    float *t_prop, *t_ell, *t_lam;
-    // lineage tags, ping-pong like the state (PF_DEBUG_LINEAGE), else NULL
-    int32_t *lin[2];
-};
-
-struct StepArgs {
-    const float *sin;                   // [5][N] resampled particles of k-1
-    float *sout;                        // [5][N] resampled particles of k
-    const pf_pe_record *rin;            // [F*M] records of k-1
-    pf_pe_record *rout;                 // [F*M] records of k
-    const uint16_t *ring;               // [F*M] pred(m) for this k, or NULL (fixed ring)
-    const DebugBufs *dbg;               // NULL unless a debug mode is on
-    Lik lik;
-    Dyn dyn;
-    uint32_t N;                         // F M N_p (< 2^31)
-    uint32_t M, np, np_top;             // np_top: largest power of two <= N_p
-    uint32_t k, key0, key1;
-    uint32_t mode, first, fixed_nex, initial_nex, cutoff_ppm, qmax;
-    uint32_t lin_in;                    // which lineage buffer holds iteration k-1
-    double inv_np;                      // 1 / N_p
-    uint32_t *err;                      // sticky numeric-error flag
-    uint32_t *nex_used;                 // [F]
-};
-
-// What a PE knows after steps 1-2 (and the inputs of steps 3-4).
-struct Prologue {
-    uint32_t pred, nex, c_own, c_pred;
-    float lam_own, lam_pred;
-};
-
-// Steps 1-2 and the renormalization constant of step 4, computed by one wave
-// of every workgroup from the M records of the previous iteration:
-//   L_glob = log sum_m W^(m)_{k-1},  P_m = floor(exp(L_m - max L) 2^20),
-//   S = sum P, D = sum P^2  ->  N_ex (Eq. 3 with PE_eff = S^2 / D).
-// Lane 0 writes the result to `out`.
-__device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t M = a.M;
-    const pf_pe_record *R = a.rin + (size_t)f * M;
-    double lmax = -INFINITY;
-    for (uint32_t i = lane; i < M; i += kWave) lmax = fmax(lmax, R[i].log_mass);
-    lmax = wave_max_d(lmax);
-    double acc = 0.0;
-    uint64_t S = 0, D = 0;
-    if (lmax != -INFINITY) {
-        for (uint32_t i = lane; i < M; i += kWave) {
-            const double e = exp(R[i].log_mass - lmax);
-            acc += e;
-            const uint64_t P = (uint64_t)floor(e * 1048576.0);
-            S += P;
-            D += P * P;
-        }
-    }
-    acc = wave_sum(acc);
-    S = wave_sum_u64(S);
-    D = wave_sum_u64(D);
-    if (lane == 0) {
-        Prologue p;
-        p.pred = (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
-        p.nex = exchange_count(S, D, M, a.np, a.mode, (int)a.first, a.fixed_nex, a.initial_nex,
-                               a.cutoff_ppm);
-        if (p.nex > a.np) p.nex = a.np;
-        const double lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
-        if (lglob == -INFINITY) {
-            p.lam_own = 0.f;
-            p.lam_pred = 0.f;
-        } else {
-            p.lam_own = (float)(R[m].log_mass - lglob);
-            p.lam_pred = (float)(R[p.pred].log_mass - lglob);
-        }
-        p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-        p.c_pred = mulshift(philox(p.pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-        *out = p;
-    }
-}
-
-// Step 3: PE m sends its slots s_t(m) = floor((t N_p + c_m) / N_ex), t < N_ex,
-// and refills them with the slots s_t(pred(m)) that pred(m) sends.  The map
-// recv[s_t(m)] = s_t(pred(m)) is built in LDS (0xFFFF = slot keeps its own
-// particle); `recv` must hold 0xFFFF for every slot on entry.
-__device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue &p, uint32_t np) {
-    for (uint32_t t = threadIdx.x; t < p.nex; t += blockDim.x) {
-        const uint32_t dst = (t * np + p.c_own) / p.nex;
-        const uint32_t src = (t * np + p.c_pred) / p.nex;
-        recv[dst] = (uint16_t)src;
-    }
-}
-
-// LDS image tile: 64 columns, up to 64 rows; holds z - B, zero outside the
-// image.  The row pitch is 11 mod 32 (and mod 64), so the patch origins of a
-// cluster of particles, which differ by a few rows and columns, fall on
-// different LDS banks.
-constexpr int kTileCols = 64, kTilePitch = 75, kTileRows = 64;
-constexpr int kMaxWaves = 16;
-
-// Dynamic LDS layout of k_step.
-struct Lds {
-    Prologue *pro;     // 1
-    int *box;          // 4 (+4 pad)
-    float *wmax;       // [16] wave maxima
-    uint32_t *wq;      // [16][4] wave totals of Q, per slot level
-    double *wsum;      // [16][6] wave sums (W, W x)
-    float *st;         // [5][np] propagated particles
-    uint32_t *cq;      // [np] inclusive sums C of the fixed-point weights
-    float *tile;       // [kTileRows][kTilePitch]
-    int32_t *lin;      // [np] (lineage only)
-};
-__device__ __forceinline__ Lds carve(unsigned char *base, uint32_t np) {
-    Lds l;
-    size_t o = 0;
-    l.wsum = (double *)(base + o);
-    o += kMaxWaves * 6 * sizeof(double);
-    l.pro = (Prologue *)(base + o);
-    o += 32;
-    l.box = (int *)(base + o);
-    o += 32;
-    l.wmax = (float *)(base + o);
-    o += kMaxWaves * sizeof(float);
-    l.wq = (uint32_t *)(base + o);
-    o += kMaxWaves * 4 * sizeof(uint32_t);
-    l.st = (float *)(base + o);
-    o += 5 * (size_t)np * sizeof(float);
-    l.cq = (uint32_t *)(base + o);
-    o += (size_t)np * sizeof(uint32_t);
-    l.tile = (float *)(base + o);
-    o += (size_t)kTileRows * kTilePitch * sizeof(float);
-    l.lin = (int32_t *)(base + o);
-    return l;
-}
-__host__ __device__ constexpr size_t lds_fixed_bytes() {
-    return kMaxWaves * 6 * sizeof(double) + 32 + 32 + kMaxWaves * sizeof(float) +
-           kMaxWaves * 4 * sizeof(uint32_t) + (size_t)kTileRows * kTilePitch * sizeof(float);
-}
-
-// Step 7 building blocks, shared by k_step and the debug entry point.
-// Thread t holds the fixed-point weights of slots t + q B (q < PPT).
-// Part 1: inclusive scans within each wave, per level q; the last lane of each
-// wave leaves the wave totals in wq[wave][q].
-template <int PPT>
-__device__ __forceinline__ void scan_levels(const uint32_t (&Q)[PPT], uint32_t (&cinc)[PPT],
-                                            uint32_t *wq) {
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) cinc[q] = wave_incl_scan_u32(Q[q]);
-    if (lane == kWave - 1)
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) wq[wave * 4 + q] = cinc[q];
-}
-// Part 2 (after a barrier): inclusive sums C in slot order written to C[],
-// returns the total T.
-template <int PPT>
-__device__ __forceinline__ uint32_t scan_finish(const uint32_t (&cinc)[PPT], const uint32_t *wq,
-                                                uint32_t *C, uint32_t np) {
-    const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-    uint32_t T = 0;
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        uint32_t level = 0, prior = 0;
-        for (uint32_t w = 0; w < nwaves; ++w) {
-            const uint32_t t = wq[w * 4 + q];
-            level += t;
-            if (w < wave) prior += t;
-        }
-        const uint32_t s = threadIdx.x + q * blockDim.x;
-        if (s < np) C[s] = T + prior + cinc[q];
-        T += level;
-    }
-    return T;
-}
-// Part 3 (after a barrier): ancestors of the outputs j = t + q B.
-template <int PPT>
-__device__ __forceinline__ void ancestors(const uint32_t *C, uint32_t np, uint32_t T, uint32_t V,
-                                          uint32_t np_top, double inv_np, uint32_t (&anc)[PPT]) {
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {   // independent searches, interleaved
-        const uint32_t j = threadIdx.x + q * blockDim.x;
-        const uint32_t tau = div_floor((uint64_t)j * T + V, np, inv_np);
-        anc[q] = (j < np) ? systematic_ancestor(C, np, tau, np_top) : 0u;
-    }
-}
-
-// One ARNA / RNA iteration; one workgroup = one PE (f, m).  Thread t owns the
-// slots s = t + q B, q < PPT (B = blockDim.x), so every global access of a
-// slot level is coalesced.
-template <int PPT, int HALF, bool POINT>
-__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int P = 2 * HALF + 1;
-    const uint32_t M = a.M, np = a.np, N = a.N;
-    const uint32_t f = blockIdx.x / M, m = blockIdx.x % M;
-    const uint32_t tid = threadIdx.x, B = blockDim.x;
-    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, nwaves = B / kWave;
-    Lds L = carve(smem, np);
-    uint16_t *recv = (uint16_t *)L.tile;   // receive map; the tile is loaded later
-    const uint32_t pe_base = blockIdx.x * np;   // (f M + m) N_p
-    const DebugBufs *D = a.dbg;
-    const int32_t *lin_in = D ? D->lin[a.lin_in] : nullptr;
-    int32_t *lin_out = D ? D->lin[1 - a.lin_in] : nullptr;
-    const bool trace = D && D->t_q;
-
-    // ---- phase 0: wave 0 redoes the master step of iteration k-1 (steps
-    // 1-2); every thread issues the loads of its own slots (most slots keep
-    // their particle) and draws the step-5 normals while they are in flight.
-    if (tid < kWave) prologue_wave(a, f, m, L.pro);
-    if (tid == 0) {
-        L.box[0] = INT_MAX;
-        L.box[1] = INT_MIN;
-        L.box[2] = INT_MAX;
-        L.box[3] = INT_MIN;
-    }
-    float x[PPT][5];
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        if (s < np) {
-            recv[s] = 0xFFFF;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.sin[c * N + pe_base + s];
-        }
-    }
-    float e[PPT][5];
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        if (s < np)
-            five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e[q]);
-    }
-    __syncthreads();   // barrier 1: prologue visible, receive map cleared
-    const Prologue p = *L.pro;
-    if (p.nex) {
-        build_receive_map(recv, p, np);
-        __syncthreads();   // barrier 1b: receive map
-    }
-
-    // ---- phase 1 (steps 3-5 P): received slots are refetched from pred(m);
-    // propagate; stage in LDS; bounding box of the patch origins.
-    int bx0 = INT_MAX, bx1 = INT_MIN, by0 = INT_MAX, by1 = INT_MIN;
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        if (s >= np) continue;
-        uint32_t gsrc = pe_base + s;
-        float lam = p.lam_own;
-        const uint32_t r = p.nex ? recv[s] : 0xFFFFu;
-        if (r != 0xFFFFu) {
-            gsrc = (f * M + p.pred) * np + r;
-            lam = p.lam_pred;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.sin[c * N + gsrc];
-        }
-        if (lin_in) L.lin[s] = lin_in[gsrc];
-        if (trace) {
-            D->t_src[pe_base + s] = (int64_t)gsrc;
-            D->t_lam[pe_base + s] = lam;
-        }
-        propagate(x[q], e[q], a.dyn);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) L.st[c * np + s] = x[q][c];
-        L.cq[s] = __float_as_uint(lam);   // parked until the likelihood is known
-        if (!POINT) {
-            int u0, v0;
-            if (patch_origin<HALF>(x[q][0], x[q][1], a.lik.W, a.lik.H, u0, v0)) {
-                bx0 = min(bx0, u0);
-                bx1 = max(bx1, u0);
-                by0 = min(by0, v0);
-                by1 = max(by1, v0);
-            }
-        }
-    }
-    bool use_tile = false, tile_inside = false;
-    int tx0 = 0, ty0 = 0;
-    if (!POINT) {
-        bx0 = wave_min_i32(bx0);
-        bx1 = wave_max_i32(bx1);
-        by0 = wave_min_i32(by0);
-        by1 = wave_max_i32(by1);
-        if (lane == 0 && bx0 <= bx1) {
-            atomicMin(&L.box[0], bx0);
-            atomicMax(&L.box[1], bx1);
-            atomicMin(&L.box[2], by0);
-            atomicMax(&L.box[3], by1);
-        }
-        __syncthreads();   // barrier 2: bounding box (receive map no longer read)
-        tx0 = L.box[0];
-        ty0 = L.box[2];
-        int th = 0;
-        if (tx0 <= L.box[1]) {   // at least one patch touches the image
-            const int tw = L.box[1] - tx0 + P;
-            th = L.box[3] - ty0 + P;
-            use_tile = tw <= kTileCols && th <= kTileRows;
-            tile_inside = tx0 >= 0 && ty0 >= 0 && tx0 + tw <= a.lik.W && ty0 + th <= a.lik.H;
-        }
-        if (use_tile) {
-            // tile pixel (r, c) is image pixel (tx0 + c, ty0 + r)
-            for (int idx = (int)tid; idx < th * kTileCols; idx += (int)B) {
-                const int r = idx / kTileCols, c = idx % kTileCols;
-                const int u = tx0 + c, v = ty0 + r;
-                const bool in = (unsigned)u < (unsigned)a.lik.W && (unsigned)v < (unsigned)a.lik.H;
-                L.tile[r * kTilePitch + c] =
-                    in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
-            }
-            __syncthreads();   // barrier 3: tile
-        }
-    } else {
-        __syncthreads();   // barrier 2: LDS staging complete
-    }
-
-    // ---- phase 2 (step 5 U): log-likelihood of every slot; u = lambda + l,
-    // one slot at a time (the particle comes back from LDS), u parked in LDS.
-    float umax = -INFINITY;
-    bool bad = false;
-#pragma unroll 1
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        if (s >= np) break;
-        float xs[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) xs[c] = L.st[c * np + s];
-        float ell;
-        if (POINT) {
-            ell = loglik_point(xs, a.lik, f);
-        } else if (use_tile) {
-            int u0, v0;
-            ell = 0.f;
-            if (patch_origin<HALF>(xs[0], xs[1], a.lik.W, a.lik.H, u0, v0)) {
-                const float *pix = L.tile + (v0 - ty0) * kTilePitch + (u0 - tx0);
-                ell = tile_inside
-                          ? patch_loglik<HALF, kFromTileInside>(xs, u0, v0, pix, kTilePitch, a.lik)
-                          : patch_loglik<HALF, kFromTile>(xs, u0, v0, pix, kTilePitch, a.lik);
-            }
-        } else {
-            ell = loglik_patch<HALF>(xs, a.lik);
-        }
-        bad |= (ell != ell);
-        const float uu = __uint_as_float(L.cq[s]) + ell;
-        umax = fmaxf(umax, uu);
-        L.cq[s] = __float_as_uint(uu);
-        if (trace) {
-            D->t_ell[pe_base + s] = ell;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) D->t_prop[c * N + pe_base + s] = xs[c];
-        }
-    }
-    if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
-    umax = wave_max_f32(umax);
-    if (lane == 0) L.wmax[wave] = umax;
-    __syncthreads();   // barrier 4: wave maxima
-    float lstar = L.wmax[0];
-    for (uint32_t w = 1; w < nwaves; ++w) lstar = fmaxf(lstar, L.wmax[w]);
-
-    // ---- phase 3 (steps 6-7): weights relative to lstar, fixed-point
-    // Q = floor(w Q_max), per-PE sums in FP64, inclusive prefix sums of Q in
-    // slot order (level q of thread t is slot t + q B).
-    const float qmaxf = (float)a.qmax;
-    double sums[6] = {0, 0, 0, 0, 0, 0};
-    uint32_t Qv[PPT], cinc[PPT];
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        Qv[q] = 0;
-        if (s < np) {
-            const float w =
-                (lstar == -INFINITY) ? 1.0f : __expf(__uint_as_float(L.cq[s]) - lstar);
-            float qf = floorf(w * qmaxf);
-            qf = (qf >= 0.f) ? fminf(qf, qmaxf) : 0.f;
-            Qv[q] = (uint32_t)qf;
-            const double wd = (double)w;
-            sums[0] += wd;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) sums[1 + c] += wd * (double)L.st[c * np + s];
-            if (trace) D->t_q[pe_base + s] = Qv[q];
-        }
-    }
-    scan_levels<PPT>(Qv, cinc, L.wq);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sums[c] = wave_total_f64(sums[c]);
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L.wsum[wave * 6 + c] = sums[c];
-    }
-    __syncthreads();   // barrier 5: wave totals
-    const uint32_t T = scan_finish<PPT>(cinc, L.wq, L.cq, np);
-    const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
-    __syncthreads();   // barrier 6: C complete
-
-    // ---- phase 4 (step 7): ancestors by search over C, gather from LDS.
-    uint32_t anc[PPT];
-    ancestors<PPT>(L.cq, np, T, V, a.np_top, a.inv_np, anc);
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t j = tid + q * B;
-        if (j >= np) continue;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) a.sout[c * N + pe_base + j] = L.st[c * np + anc[q]];
-        if (lin_out) lin_out[pe_base + j] = L.lin[anc[q]];
-        if (trace) D->t_anc[pe_base + j] = anc[q];
-    }
-
-    // ---- steps 8-9: every particle now carries W^(m)_k; publish the record
-    if (tid == 0) {
-        double tot[6] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t w = 0; w < nwaves; ++w)
-            for (int c = 0; c < 6; ++c) tot[c] += L.wsum[w * 6 + c];
-        pf_pe_record r;
-        r.log_mass = (lstar == -INFINITY) ? -INFINITY : (double)lstar + log(tot[0]);
-        for (int c = 0; c < 5; ++c) r.xhat[c] = tot[1 + c] / tot[0];
-        r.lstar = lstar;
-        r.total_q = T;
-        a.rout[blockIdx.x] = r;
-        if (m == 0) a.nex_used[f] = p.nex;
-        if (trace) {
-            D->t_pred[blockIdx.x] = p.pred;
-            D->t_v[blockIdx.x] = V;
-        }
-    }
-}
-
-// Step 1 for kRingSteps iterations at once: Fisher-Yates (Durstenfeld,
-// i = M-1 .. 1, j = floor(r_i (i + 1) / 2^32)) over the M labels; the ring
-// visits perm[0], perm[1], ... and closes.  Grid (steps, F).
-__global__ __launch_bounds__(256) void k_ring(uint16_t *tab, uint32_t base, uint32_t F,
-                                              uint32_t M, uint32_t key0, uint32_t key1) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t *perm = (uint16_t *)smem;
-    uint16_t *jd = perm + M;
-    const uint32_t k = base + blockIdx.x, f = blockIdx.y;
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-        perm[i] = (uint16_t)i;
-        jd[i] = (i == 0) ? 0 : (uint16_t)mulshift(philox(i, k, f, kTagRing << 24, key0, key1).x,
-                                                  i + 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (uint32_t i = M - 1; i >= 1; --i) {
-            const uint32_t j = jd[i];
-            const uint16_t t = perm[i];
-            perm[i] = perm[j];
-            perm[j] = t;
-        }
-    }
-    __syncthreads();
-    uint16_t *out = tab + ((size_t)blockIdx.x * F + f) * M;
-    for (uint32_t t = threadIdx.x; t < M; t += blockDim.x)
-        out[perm[t]] = perm[(t + M - 1) % M];
-}
-
-// Initialization (Sec. V).  Tracking: every particle at the truth.
-// Information sharing: PE 0 uniform in the radius-2 disk around the true
-// position with the true velocity and intensity; other PEs uniform over the
-// image, velocity in [-2, 2]^2, intensity in [0, 2 I].
-__global__ void k_init(float *st, pf_pe_record *rec, int32_t *lin, const float *truth,
-                       uint64_t N, uint32_t M, uint32_t np, uint32_t W, uint32_t H,
-                       uint32_t infoshare, uint32_t key0, uint32_t key1, uint32_t FM) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < FM) {
-        pf_pe_record r = {};
-        r.log_mass = 0.0;
-        rec[g] = r;
-    }
-    if (g >= N) return;
-    const uint32_t pe = (uint32_t)(g / np), s = (uint32_t)(g % np);
-    const uint32_t f = pe / M, m = pe % M;
-    const float *t = truth + 5 * f;
-    float v[5] = {t[0], t[1], t[2], t[3], t[4]};
-    if (infoshare) {
-        const uint32_t j = m * np + s;
-        const u4 r0 = philox(j, 0, f, (kTagInit << 24) | 0u, key0, key1);
-        const u4 r1 = philox(j, 0, f, (kTagInit << 24) | 1u, key0, key1);
-        if (m == 0) {
-            const float rad = 2.0f * __builtin_sqrtf(unif24(r0.x));
-            const float ang = unif24(r0.y);
-            v[0] = t[0] + rad * cos_rev(ang);
-            v[1] = t[1] + rad * sin_rev(ang);
-        } else {
-            v[0] = -0.5f + (float)W * unif24(r0.x);
-            v[1] = -0.5f + (float)H * unif24(r0.y);
-            v[2] = -2.0f + 4.0f * unif24(r0.z);
-            v[3] = -2.0f + 4.0f * unif24(r0.w);
-            v[4] = 2.0f * t[4] * unif24(r1.x);
-        }
-    }
-    for (int c = 0; c < 5; ++c) st[c * N + g] = v[c];
-    if (lin) lin[g] = (int32_t)m;
-}
-
-// Master step of iteration k (Alg. 3, steps 9-10) for reporting: W_k, the
-// global estimate x_k = sum_m W^(m) x^m / W_k, PE_eff and the next N_ex.
-__global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, EstDev *est,
-                                                uint32_t M, uint32_t np, uint32_t mode,
-                                                uint32_t fixed_nex, uint32_t cutoff_ppm) {
-    __shared__ double red[kRedDoubles];
-    const uint32_t f = blockIdx.x;
-    const pf_pe_record *R = rec + (size_t)f * M;
-    double lmax = -INFINITY;
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) lmax = fmax(lmax, R[i].log_mass);
-    lmax = block_max_d(lmax, red);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    uint64_t sd[2] = {0, 0};
-    if (lmax != -INFINITY) {
-        for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-            const double e = exp(R[i].log_mass - lmax);
-            const uint64_t P = (uint64_t)floor(e * 1048576.0);
-            sd[0] += P;
-            sd[1] += P * P;
-            acc[0] += e;
-            if (e > 0.0)
-                for (int c = 0; c < 5; ++c) acc[1 + c] += e * R[i].xhat[c];
-        }
-    }
-    block_sum<6>(acc, red);
-    block_sum_u64(sd, (uint64_t *)red);
-    if (threadIdx.x == 0) {
-        EstDev o;
-        o.log_mass_glob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
-        for (int c = 0; c < 5; ++c) o.xhat[c] = acc[1 + c] / acc[0];
-        o.pe_eff = sd[1] ? (double)sd[0] * (double)sd[0] / (double)sd[1] : 0.0;
-        o.log_z = o.log_mass_glob - log((double)np);
-        o.n_ex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
-        o.pad = 0;
-        est[f] = o;
-    }
-}
-
-// pf_exchange: steps 1-3 of the next iteration, exported as a source map.
-__global__ __launch_bounds__(256) void k_exchange_map(StepArgs a, int64_t *src) {
-    __shared__ Prologue pro;
-    __shared__ uint16_t recv[PF_MAX_PER_PE];
-    const uint32_t f = blockIdx.x / a.M, m = blockIdx.x % a.M;
-    if (threadIdx.x < kWave) prologue_wave(a, f, m, &pro);
-    for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) recv[s] = 0xFFFF;
-    __syncthreads();
-    const Prologue p = pro;
-    build_receive_map(recv, p, a.np);
-    __syncthreads();
-    for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) {
-        const uint32_t r = recv[s];
-        const uint64_t g = (r == 0xFFFFu) ? (uint64_t)blockIdx.x * a.np + s
-                                          : ((uint64_t)f * a.M + p.pred) * a.np + r;
-        src[(uint64_t)blockIdx.x * a.np + s] = (int64_t)g;
-    }
-}
-
-// Debug entry points: the integer stages alone, same device code as k_step.
-template <int PPT>
-__global__ __launch_bounds__(1024) void k_resample_q(const uint32_t *q, const uint32_t *v,
-                                                     uint32_t *anc_out, uint32_t np,
-                                                     uint32_t np_top, double inv_np) {
-    __shared__ uint32_t wq[kMaxWaves * 4];
-    __shared__ uint32_t C[PF_MAX_PER_PE];
-    const uint32_t base = blockIdx.x * np;
-    uint32_t Qv[PPT], cinc[PPT], anc[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint32_t s = threadIdx.x + k * blockDim.x;
-        Qv[k] = (s < np) ? q[base + s] : 0u;
-    }
-    scan_levels<PPT>(Qv, cinc, wq);
-    __syncthreads();
-    const uint32_t T = scan_finish<PPT>(cinc, wq, C, np);
-    __syncthreads();
-    const uint32_t V = v[blockIdx.x];
-    ancestors<PPT>(C, np, T, V, np_top, inv_np, anc);
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint32_t j = threadIdx.x + k * blockDim.x;
-        if (j < np) anc_out[base + j] = anc[k];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_nex(const uint32_t *P, uint32_t M, uint32_t np,
-                                             uint32_t mode, int first, uint32_t fixed_nex,
-                                             uint32_t initial_nex, uint32_t cutoff_ppm,
-                                             uint32_t *out) {
-    __shared__ uint64_t red[64];
-    uint64_t sd[2] = {0, 0};
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-        sd[0] += P[i];
-        sd[1] += (uint64_t)P[i] * P[i];
-    }
-    block_sum_u64(sd, red);
-    if (threadIdx.x == 0)
-        *out = exchange_count(sd[0], sd[1], M, np, mode, first, fixed_nex, initial_nex,
-                              cutoff_ppm);
-}
-
-__global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t n,
-                         uint32_t *out) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const u4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
-    out[4 * i] = r.x;
-    out[4 * i + 1] = r.y;
-    out[4 * i + 2] = r.z;
-    out[4 * i + 3] = r.w;
-}
 
 // ---------------------------------------------------------------- host side
 uint32_t fixed_count(float ratio, uint32_t np) {
@@ -982,6 +370,33 @@ int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_st
         if (rc != PF_OK) return rc;
     }
     return PF_OK;
+}
+
+int pf_run_timed(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
+                 float *host_ms_out) {
+    if (!c || !host_ms_out || (!d_frames && n_steps)) return PF_EINVAL;
+    if (n_steps == 0) return PF_OK;
+    hipEvent_t *ev = (hipEvent_t *)calloc(2 * (size_t)n_steps, sizeof(hipEvent_t));
+    if (!ev) return PF_ENOMEM;
+    int rc = PF_OK;
+    uint32_t made = 0;
+    for (; made < 2 * n_steps; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) {
+            rc = PF_EHIP;
+            break;
+        }
+    for (uint32_t i = 0; rc == PF_OK && i < n_steps; ++i) {
+        if (hipEventRecord(ev[2 * i], c->stream) != hipSuccess) rc = PF_EHIP;
+        if (rc == PF_OK) rc = launch_step(c, d_frames + (size_t)i * frame_stride);
+        if (rc == PF_OK && hipEventRecord(ev[2 * i + 1], c->stream) != hipSuccess) rc = PF_EHIP;
+    }
+    if (rc == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = PF_EHIP;
+    for (uint32_t i = 0; rc == PF_OK && i < n_steps; ++i)
+        if (hipEventElapsedTime(&host_ms_out[i], ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+            rc = PF_EHIP;
+    for (uint32_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    free(ev);
+    return rc;
 }
 
 int pf_exchange(pf_ctx *c, int64_t *d_src_map) {

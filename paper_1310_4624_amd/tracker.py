@@ -89,6 +89,21 @@ class Tracker:
             raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
         nat.check(nat.lib().pf_run(self._h, _dev_ptr(frames, "frames"), n, stride), "pf_run")
 
+    def run_timed(self, frames, n_steps: int | None = None) -> np.ndarray:
+        """Like run(); returns each iteration's duration in ms (HIP events on
+        the context's stream, recorded by the library around its launches)."""
+        n = frames.shape[0] if n_steps is None else n_steps
+        if n > frames.shape[0]:
+            raise ValueError("more steps than frames")
+        stride = int(np.prod(frames.shape[1:]))
+        if stride != self.frame_numel():
+            raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
+        out = np.zeros(n, np.float32)
+        nat.check(nat.lib().pf_run_timed(self._h, _dev_ptr(frames, "frames"), n, stride,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                  "pf_run_timed")
+        return out
+
     def exchange(self, src_map=None) -> None:
         p = None
         if src_map is not None:
