@@ -2,7 +2,9 @@
 // MI355X (gfx950), exported through the C interface in include/arna.h.
 //
 // Data layout in HBM (one context):
-//   state[2][5][N] float32   ping-pong particle buffers, component-major
+//   prop[2][5][N] float32    ping-pong propagated particles, component-major
+//   anc[2][N] uint16         ping-pong ancestors: resampled slot s of PE p is
+//                            propagated particle anc[p N_p + s] of that PE
 //   rec[2][F*M]              per-PE records (log W^(m), x^m, lstar, T)
 //   ring[R][F][M] uint16     pred(m) of R upcoming iterations (ARNA only)
 // One workgroup is one PE: it gathers its N_p particles (own slots plus the
@@ -63,7 +65,8 @@ struct pf_ctx {
     uint64_t N, FM;
     uint32_t block, ppt, half;
     size_t lds;
-    float *state[2];
+    float *prop[2];
+    uint16_t *anc[2];
     pf_pe_record *rec[2];
     int32_t *lin[2];
     int cur;                       // buffers holding iteration `step`
@@ -157,7 +160,8 @@ int validate(const pf_config *c) {
 }
 
 void free_all(pf_ctx *c) {
-    void *ptrs[] = {c->state[0], c->state[1], c->rec[0], c->rec[1], c->lin[0], c->lin[1],
+    void *ptrs[] = {c->prop[0], c->prop[1], c->anc[0], c->anc[1], c->rec[0], c->rec[1],
+                    c->lin[0], c->lin[1],
                     c->ring_tab, c->err, c->nex_used, c->est, c->t_pred, c->t_q, c->t_anc,
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg};
     for (void *p : ptrs)
@@ -181,8 +185,10 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     StepArgs a;
     memset(&a, 0, sizeof(a));
     const int nxt = 1 - c->cur;
-    a.sin = c->state[c->cur];
-    a.sout = c->state[nxt];
+    a.pin = c->prop[c->cur];
+    a.ain = c->anc[c->cur];
+    a.pout = c->prop[nxt];
+    a.aout = c->anc[nxt];
     a.rin = c->rec[c->cur];
     a.rout = c->rec[nxt];
     a.ring = (c->cfg.mode == PF_MODE_ARNA && c->cfg.n_pe > 1)
@@ -195,8 +201,6 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     a.N = (uint32_t)c->N;
     a.M = c->cfg.n_pe;
     a.np = c->cfg.n_per_pe;
-    a.np_top = 1u << (31 - __builtin_clz(c->cfg.n_per_pe));
-    a.inv_np = 1.0 / (double)c->cfg.n_per_pe;
     a.k = (uint32_t)k;
     a.key0 = c->key0;
     a.key1 = c->key1;
@@ -286,7 +290,8 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     const uint64_t N = c->N;
     rc = PF_OK;
     for (int i = 0; i < 2 && rc == PF_OK; ++i) {
-        rc = dev_alloc(&c->state[i], 5 * N);
+        rc = dev_alloc(&c->prop[i], 5 * N);
+        if (rc == PF_OK) rc = dev_alloc(&c->anc[i], N);
         if (rc == PF_OK) rc = dev_alloc(&c->rec[i], c->FM);
         if (rc == PF_OK && lineage) rc = dev_alloc(&c->lin[i], N);
     }
@@ -340,7 +345,8 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     if (rc == PF_OK) {
         const uint64_t work = N > c->FM ? N : c->FM;
         hipLaunchKernelGGL(k_init, dim3((uint32_t)((work + 255) / 256)), dim3(256), 0, c->stream,
-                           c->state[0], c->rec[0], c->lin[0], d_truth, N, M, np, cfg->width,
+                           c->prop[0], c->anc[0], c->rec[0], c->lin[0], d_truth, N, M, np,
+                           cfg->width,
                            cfg->height, cfg->init_mode == PF_INIT_INFOSHARE ? 1u : 0u, c->key0,
                            c->key1, (uint32_t)c->FM);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
@@ -503,7 +509,19 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
     HIP_OK(hipStreamSynchronize(c->stream));
     const void *src = nullptr;
     switch (which) {
-        case PF_DBG_STATE: src = c->state[c->cur]; break;
+        case PF_DBG_STATE: {
+            float *tmp = nullptr;
+            int rc = dev_alloc(&tmp, 5 * c->N);
+            if (rc != PF_OK) return rc;
+            hipLaunchKernelGGL(k_materialize, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0,
+                               c->stream, c->prop[c->cur], c->anc[c->cur], tmp, (uint32_t)c->N,
+                               c->cfg.n_per_pe);
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+                hipMemcpy(dst, tmp, need, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = PF_EHIP;
+            (void)hipFree(tmp);
+            return rc;
+        }
         case PF_DBG_PE_RECORDS: src = c->rec[c->cur]; break;
         case PF_DBG_NEX: src = c->nex_used; break;
         case PF_DBG_RING: src = c->t_pred; break;
@@ -536,7 +554,11 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
 int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, uint64_t step) {
     if (!c || !state) return PF_EINVAL;
     HIP_OK(hipStreamSynchronize(c->stream));
-    HIP_OK(hipMemcpy(c->state[c->cur], state, 5 * c->N * sizeof(float), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->prop[c->cur], state, 5 * c->N * sizeof(float), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_identity, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream,
+                       c->anc[c->cur], (uint32_t)c->N, c->cfg.n_per_pe);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
     pf_pe_record *rec = (pf_pe_record *)calloc(c->FM, sizeof(pf_pe_record));
     if (!rec) return PF_ENOMEM;
     for (uint64_t i = 0; i < c->FM; ++i) rec[i].log_mass = log_mass ? log_mass[i] : 0.0;
@@ -577,14 +599,12 @@ int pf_debug_resample_q(const uint32_t *q, uint32_t n_blocks, uint32_t n_p, cons
             hipMemcpy(dv, v, (size_t)n_blocks * 4, hipMemcpyHostToDevice) != hipSuccess)
             rc = PF_EHIP;
         if (rc == PF_OK) {
-            const uint32_t top = 1u << (31 - __builtin_clz(n_p));
-            const double inv = 1.0 / (double)n_p;
             if (n_p > 1024)
                 hipLaunchKernelGGL(k_resample_q<4>, dim3(n_blocks), dim3(B), 0, 0, dq, dv, da,
-                                   n_p, top, inv);
+                                   n_p);
             else
                 hipLaunchKernelGGL(k_resample_q<1>, dim3(n_blocks), dim3(B), 0, 0, dq, dv, da,
-                                   n_p, top, inv);
+                                   n_p);
             if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
                 hipMemcpy(anc_out, da, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 rc = PF_EHIP;

@@ -185,12 +185,17 @@ __device__ __forceinline__ float patch_loglik(const float s[5], int u0, int v0, 
     }
     float acc = 0.f;
     if (SRC == kFromTile || SRC == kFromTileInside) {
+        // every LDS read of the patch is issued before the first product
+        float z[P * P];
+#pragma unroll
+        for (int jv = 0; jv < P; ++jv)
+#pragma unroll
+            for (int ju = 0; ju < P; ++ju) z[jv * P + ju] = pix[jv * pitch + ju];
 #pragma unroll
         for (int jv = 0; jv < P; ++jv) {
-            const float *row = pix + jv * pitch;
             float r = 0.f;
 #pragma unroll
-            for (int ju = 0; ju < P; ++ju) r += gx[ju] * row[ju];
+            for (int ju = 0; ju < P; ++ju) r += gx[ju] * z[jv * P + ju];
             acc += gy[jv] * r;
         }
         const float I = s[4];
@@ -426,23 +431,33 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t *c, int n, int
     return total;
 }
 
-// a_j = min { i : n C_i > j T + V } over the inclusive sums C[0..n).  For
-// integer C this is min { i : C_i > tau } with tau = floor((j T + V) / n), a
-// 32-bit lower bound found by binary lifting (C[n-1] = T > tau always).
-__device__ __forceinline__ uint32_t systematic_ancestor(const uint32_t *C, uint32_t n,
-                                                        uint32_t tau, uint32_t top) {
-    uint32_t pos = 0;   // number of leading entries <= tau
-    for (uint32_t step = top; step > 0; step >>= 1)
-        if (pos + step <= n && C[pos + step - 1] <= tau) pos += step;
-    return pos;
+// Wave-wide inclusive prefix maximum of unsigned values (identity 0), and the
+// exclusive one (the inclusive value of the previous lane, 0 for lane 0).
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
+    return wave_scan_bits(v, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
 }
-// floor(num / n) for num < 2^53, n >= 1, through a double reciprocal and one
-// integer correction either way.
-__device__ __forceinline__ uint32_t div_floor(uint64_t num, uint32_t n, double inv_n) {
-    uint64_t q = (uint64_t)((double)num * inv_n);
-    if (q * n > num) --q;
-    else if ((q + 1) * n <= num) ++q;
-    return (uint32_t)q;
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {   // lane i gets lane i-1
+    return dpp<0x138, 0xF>(v, 0u);
+}
+
+// floor(num / d) for num < 2^53 and a 32-bit divisor d.
+__device__ __forceinline__ uint32_t div_floor_T(uint64_t num, uint32_t d, double inv_d) {
+    const uint32_t q = (uint32_t)((double)num * inv_d);
+    const uint64_t qd = (uint64_t)q * d;
+    const uint32_t down = (uint32_t)(qd > num);
+    const uint32_t up = (uint32_t)(qd + d <= num);
+    return q - down + up;
+}
+
+// First output of particle i in systematic resampling: the number of
+// pointers j T + V (j >= 0) below n E_i, where E_i = C_i - Q_i is the
+// exclusive cumulative weight: ceil((n E_i - V) / T), or 0 if n E_i <= V.
+// Exact for n E_i < 2^53 (a double reciprocal of T and one integer correction).
+__device__ __forceinline__ uint32_t first_offspring(uint32_t E, uint32_t n, uint32_t T, uint32_t V,
+                                                    double inv_T) {
+    const uint64_t nE = (uint64_t)n * E;
+    if (nE <= V) return 0;
+    return div_floor_T(nE - V + T - 1, T, inv_T);
 }
 
 // ------------------------------------------------------- 128-bit integers

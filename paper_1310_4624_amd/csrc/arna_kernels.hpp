@@ -39,8 +39,13 @@ struct DebugBufs {
 };
 
 struct StepArgs {
-    const float *sin;                   // [5][N] resampled particles of k-1
-    float *sout;                        // [5][N] resampled particles of k
+    // Particles are kept lazily: the propagated particles of an iteration and,
+    // per slot, the ancestor the resampling picked; resampled slot s of PE p
+    // is propagated particle anc[p N_p + s] of that PE.
+    const float *pin;                   // [5][N] propagated particles of k-1
+    const uint16_t *ain;                // [N] ancestors of k-1 (slot within the PE)
+    float *pout;                        // [5][N] propagated particles of k
+    uint16_t *aout;                     // [N] ancestors of k
     const pf_pe_record *rin;            // [F*M] records of k-1
     pf_pe_record *rout;                 // [F*M] records of k
     const uint16_t *ring;               // [F*M] pred(m) for this k, or NULL (fixed ring)
@@ -48,11 +53,10 @@ struct StepArgs {
     Lik lik;
     Dyn dyn;
     uint32_t N;                         // F M N_p (< 2^31)
-    uint32_t M, np, np_top;             // np_top: largest power of two <= N_p
+    uint32_t M, np;
     uint32_t k, key0, key1;
     uint32_t mode, first, fixed_nex, initial_nex, cutoff_ppm, qmax;
     uint32_t lin_in;                    // which lineage buffer holds iteration k-1
-    double inv_np;                      // 1 / N_p
     uint32_t *err;                      // sticky numeric-error flag
     uint32_t *nex_used;                 // [F]
 };
@@ -181,37 +185,66 @@ __device__ __forceinline__ void scan_levels(const uint32_t (&Q)[PPT], uint32_t (
 #pragma unroll
         for (int q = 0; q < PPT; ++q) wq[wave * 4 + q] = cinc[q];
 }
-// Part 2 (after a barrier): inclusive sums C in slot order written to C[],
-// returns the total T.
+// Part 2 (after a barrier): inclusive sums C of this thread's slots, in slot
+// order, and the total T.  The (level, wave) totals, 64 values in slot order,
+// are scanned across the lanes of every wave at once (lane q 16 + w holds level
+// q of wave w), so no further barrier is needed.
 template <int PPT>
-__device__ __forceinline__ uint32_t scan_finish(const uint32_t (&cinc)[PPT], const uint32_t *wq,
-                                                uint32_t *C, uint32_t np) {
-    const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-    uint32_t T = 0;
+__device__ __forceinline__ uint32_t scan_finish(uint32_t (&cinc)[PPT], const uint32_t *wq) {
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t nwaves = blockDim.x / kWave;
+    const uint32_t lq = lane / 16, lw = lane % 16;
+    const uint32_t mine = (lq < (uint32_t)PPT && lw < nwaves) ? wq[lw * 4 + lq] : 0u;
+    const uint32_t incl = wave_incl_scan_u32(mine);
+    const uint32_t T = lane63(incl);
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        uint32_t level = 0, prior = 0;
-        for (uint32_t w = 0; w < nwaves; ++w) {
-            const uint32_t t = wq[w * 4 + q];
-            level += t;
-            if (w < wave) prior += t;
-        }
-        const uint32_t s = threadIdx.x + q * blockDim.x;
-        if (s < np) C[s] = T + prior + cinc[q];
-        T += level;
+        const uint32_t src = (uint32_t)q * 16 + wave;
+        cinc[q] += (uint32_t)__builtin_amdgcn_readlane((int)(incl - mine), (int)src);
     }
     return T;
 }
-// Part 3 (after a barrier): ancestors of the outputs j = t + q B.
+
+// Part 3: every particle with offspring marks its first output rank,
+// mark[first_offspring(i)] = max(i); `mark` (>= n entries) must be zero.
 template <int PPT>
-__device__ __forceinline__ void ancestors(const uint32_t *C, uint32_t np, uint32_t T, uint32_t V,
-                                          uint32_t np_top, double inv_np, uint32_t (&anc)[PPT]) {
+__device__ __forceinline__ void mark_offspring(const uint32_t (&Q)[PPT], const uint32_t (&C)[PPT],
+                                               uint32_t n, uint32_t T, uint32_t V, uint32_t *mark) {
+    const double inv_T = 1.0 / (double)T;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {   // independent searches, interleaved
-        const uint32_t j = threadIdx.x + q * blockDim.x;
-        const uint32_t tau = div_floor((uint64_t)j * T + V, np, inv_np);
-        anc[q] = (j < np) ? systematic_ancestor(C, np, tau, np_top) : 0u;
+    for (int q = 0; q < PPT; ++q) {
+        const uint32_t s = threadIdx.x + q * blockDim.x;
+        if (s < n && Q[q] > 0) {
+            const uint32_t j = first_offspring(C[q] - Q[q], n, T, V, inv_T);
+            if (j < n) atomicMax(&mark[j], s);
+        }
     }
+}
+
+// Part 4 (after a barrier): the ancestor of output rank j is the largest
+// particle that marked a rank <= j, i.e. min { i : n C_i > j T + V }.
+// Thread t resolves the consecutive ranks t PPT + q; `wtmp` holds one value per
+// wave.  Contains one barrier.
+template <int PPT>
+__device__ __forceinline__ void ancestors_from_marks(const uint32_t *mark, uint32_t n,
+                                                     uint32_t *wtmp, uint32_t (&anc)[PPT]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t j0 = threadIdx.x * PPT;
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const uint32_t m = (j0 + q < n) ? mark[j0 + q] : 0u;
+        run = m > run ? m : run;
+        anc[q] = run;
+    }
+    const uint32_t incl = wave_incl_max_u32(run);
+    const uint32_t excl = wave_shr1(incl);
+    if (lane == kWave - 1) wtmp[wave] = incl;
+    __syncthreads();
+    uint32_t before = excl;
+    for (uint32_t w = 0; w < wave; ++w) before = wtmp[w] > before ? wtmp[w] : before;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) anc[q] = anc[q] > before ? anc[q] : before;
 }
 
 // One ARNA / RNA iteration; one workgroup = one PE (f, m).  Thread t owns the
@@ -243,15 +276,23 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         L.box[2] = INT_MAX;
         L.box[3] = INT_MIN;
     }
+    uint32_t own[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const uint32_t s = tid + q * B;
+        own[q] = 0;
+        if (s < np) {
+            recv[s] = 0xFFFF;
+            own[q] = a.ain[pe_base + s];
+        }
+    }
     float x[PPT][5];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const uint32_t s = tid + q * B;
-        if (s < np) {
-            recv[s] = 0xFFFF;
+        if (s < np)
 #pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.sin[c * N + pe_base + s];
-        }
+            for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pe_base + own[q]];
     }
     float e[PPT][5];
 #pragma unroll
@@ -278,10 +319,12 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         float lam = p.lam_own;
         const uint32_t r = p.nex ? recv[s] : 0xFFFFu;
         if (r != 0xFFFFu) {
-            gsrc = (f * M + p.pred) * np + r;
+            const uint32_t pred_base = (f * M + p.pred) * np;
+            gsrc = pred_base + r;
             lam = p.lam_pred;
+            const uint32_t pa = a.ain[gsrc];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.sin[c * N + gsrc];
+            for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pred_base + pa];
         }
         if (lin_in) L.lin[s] = lin_in[gsrc];
         if (trace) {
@@ -290,7 +333,10 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         }
         propagate(x[q], e[q], a.dyn);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) L.st[c * np + s] = x[q][c];
+        for (int c = 0; c < 5; ++c) {
+            L.st[c * np + s] = x[q][c];
+            a.pout[c * N + pe_base + s] = x[q][c];
+        }
         L.cq[s] = __float_as_uint(lam);   // parked until the likelihood is known
         if (!POINT) {
             int u0, v0;
@@ -407,26 +453,33 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         }
     }
     scan_levels<PPT>(Qv, cinc, L.wq);
+    uint32_t *mark = (uint32_t *)L.tile;   // the tile is no longer read
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const uint32_t s = tid + q * B;
+        if (s < np) mark[s] = 0;
+    }
 #pragma unroll
     for (int c = 0; c < 6; ++c) sums[c] = wave_total_f64(sums[c]);
     if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) L.wsum[wave * 6 + c] = sums[c];
     }
-    __syncthreads();   // barrier 5: wave totals
-    const uint32_t T = scan_finish<PPT>(cinc, L.wq, L.cq, np);
+    __syncthreads();   // barrier 5: wave totals, marks cleared
+    const uint32_t T = scan_finish<PPT>(cinc, L.wq);
     const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
-    __syncthreads();   // barrier 6: C complete
+    mark_offspring<PPT>(Qv, cinc, np, T, V, mark);
+    __syncthreads();   // barrier 6: marks complete
 
-    // ---- phase 4 (step 7): ancestors by search over C, gather from LDS.
+    // ---- phase 4 (step 7): ancestors as prefix maxima of the marks; only the
+    // indices are stored (the propagated particles went out in phase 1).
     uint32_t anc[PPT];
-    ancestors<PPT>(L.cq, np, T, V, a.np_top, a.inv_np, anc);
+    ancestors_from_marks<PPT>(mark, np, L.wq, anc);
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const uint32_t j = tid + q * B;
+        const uint32_t j = tid * PPT + q;
         if (j >= np) continue;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) a.sout[c * N + pe_base + j] = L.st[c * np + anc[q]];
+        a.aout[pe_base + j] = (uint16_t)anc[q];
         if (lin_out) lin_out[pe_base + j] = L.lin[anc[q]];
         if (trace) D->t_anc[pe_base + j] = anc[q];
     }
@@ -483,7 +536,7 @@ __global__ __launch_bounds__(256) void k_ring(uint16_t *tab, uint32_t base, uint
 // Information sharing: PE 0 uniform in the radius-2 disk around the true
 // position with the true velocity and intensity; other PEs uniform over the
 // image, velocity in [-2, 2]^2, intensity in [0, 2 I].
-__global__ void k_init(float *st, pf_pe_record *rec, int32_t *lin, const float *truth,
+__global__ void k_init(float *st, uint16_t *anc, pf_pe_record *rec, int32_t *lin, const float *truth,
                        uint64_t N, uint32_t M, uint32_t np, uint32_t W, uint32_t H,
                        uint32_t infoshare, uint32_t key0, uint32_t key1, uint32_t FM) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -515,7 +568,24 @@ __global__ void k_init(float *st, pf_pe_record *rec, int32_t *lin, const float *
         }
     }
     for (int c = 0; c < 5; ++c) st[c * N + g] = v[c];
+    anc[g] = (uint16_t)s;
     if (lin) lin[g] = (int32_t)m;
+}
+
+// Resampled particles of the last iteration, out[c][g] = prop[c][anc of g]
+// (checkpoints and pf_debug_get).
+__global__ void k_materialize(const float *prop, const uint16_t *anc, float *out, uint32_t N,
+                              uint32_t np) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const uint32_t src = (g / np) * np + anc[g];
+    for (int c = 0; c < 5; ++c) out[(size_t)c * N + g] = prop[(size_t)c * N + src];
+}
+
+// Identity ancestors (after a state is set from the host).
+__global__ void k_identity(uint16_t *anc, uint32_t N, uint32_t np) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < N) anc[g] = (uint16_t)(g % np);
 }
 
 // Master step of iteration k (Alg. 3, steps 9-10) for reporting: W_k, the
@@ -578,26 +648,26 @@ __global__ __launch_bounds__(256) void k_exchange_map(StepArgs a, int64_t *src) 
 // Debug entry points: the integer stages alone, same device code as k_step.
 template <int PPT>
 __global__ __launch_bounds__(1024) void k_resample_q(const uint32_t *q, const uint32_t *v,
-                                                     uint32_t *anc_out, uint32_t np,
-                                                     uint32_t np_top, double inv_np) {
+                                                     uint32_t *anc_out, uint32_t np) {
     __shared__ uint32_t wq[kMaxWaves * 4];
-    __shared__ uint32_t C[PF_MAX_PER_PE];
+    __shared__ uint32_t mark[PF_MAX_PER_PE];
     const uint32_t base = blockIdx.x * np;
     uint32_t Qv[PPT], cinc[PPT], anc[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const uint32_t s = threadIdx.x + k * blockDim.x;
         Qv[k] = (s < np) ? q[base + s] : 0u;
+        if (s < np) mark[s] = 0;
     }
     scan_levels<PPT>(Qv, cinc, wq);
     __syncthreads();
-    const uint32_t T = scan_finish<PPT>(cinc, wq, C, np);
+    const uint32_t T = scan_finish<PPT>(cinc, wq);
+    mark_offspring<PPT>(Qv, cinc, np, T, v[blockIdx.x], mark);
     __syncthreads();
-    const uint32_t V = v[blockIdx.x];
-    ancestors<PPT>(C, np, T, V, np_top, inv_np, anc);
+    ancestors_from_marks<PPT>(mark, np, wq, anc);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const uint32_t j = threadIdx.x + k * blockDim.x;
+        const uint32_t j = threadIdx.x * PPT + k;
         if (j < np) anc_out[base + j] = anc[k];
     }
 }
