@@ -8,8 +8,10 @@ can take their inputs from it.
 Frames stand in for the benchmark sequences of Sec. V (512 x 512 fluorescence
 microscopy frames with small bright spots, Fig. 1), which are not available:
 pixel = B + sum_spots I0 exp(-d^2 / (2 s^2)) + sigma_n N(0, 1), stored as float32.
-Spot trajectories follow the nearly-constant-velocity model (constant velocity
-for the small workload), reflected at a margin.
+Spot trajectories follow the nearly-constant-velocity model with a small
+acceleration noise q_true (constant velocity for the small workload); start
+boxes and speeds keep the spots away from the image margin over the sequence
+(a reflection at the margin would be a velocity jump no NCV filter follows).
 """
 from __future__ import annotations
 
@@ -41,7 +43,8 @@ WORKLOADS = {
                     psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5),
         seq=dict(width=512, height=512, frames=100,
                  intensities=[2.0 * s for s in np.linspace(2.0, 6.0, 4)], motion="ncv",
-                 speed=(0.5, 2.0), start_box=(64.0, 448.0), margin=16.0, min_sep=24.0),
+                 speed=(0.5, 1.0), start_box=(160.0, 352.0), margin=16.0, min_sep=24.0,
+                 q_true=0.001),
     ),
     # ARNA information sharing: 1 spot of SNR 4, 512^2, 200 frames, 256 PEs x 4096.
     "arna_infoshare_512_256x4096": dict(
@@ -50,7 +53,8 @@ WORKLOADS = {
                     fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
                     psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5),
         seq=dict(width=512, height=512, frames=200, intensities=[8.0], motion="ncv",
-                 speed=(0.5, 2.0), start_box=(64.0, 448.0), margin=16.0, min_sep=24.0),
+                 speed=(0.3, 0.6), start_box=(192.0, 320.0), margin=16.0, min_sep=24.0,
+                 q_true=0.001),
     ),
 }
 
@@ -133,7 +137,7 @@ def make_sequence(workload: str, seed: int = 1000, frames: int | None = None) ->
     rng = np.random.Generator(np.random.PCG64(seed))
     truth = trajectories(rng, len(sq["intensities"]), K, sq["width"], sq["height"],
                          sq["intensities"], sq["motion"], sq["speed"], sq["start_box"],
-                         sq["margin"], sq["min_sep"], q=fl["q"])
+                         sq["margin"], sq["min_sep"], q=sq.get("q_true", fl["q"]))
     out = np.zeros((K, sq["height"], sq["width"]), np.float32)
     for k in range(1, K + 1):
         out[k - 1] = render(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
