@@ -52,10 +52,7 @@ uint32_t block_of(uint32_t np) {
     if (np > 1024) return 1024;
     return (np + 63) / 64 * 64;
 }
-size_t step_lds(uint32_t np, bool lineage) {
-    return lds_fixed_bytes() + 5 * (size_t)np * 4 + (size_t)np * 4 +
-           (lineage ? (size_t)np * 4 : 0);
-}
+size_t step_lds(uint32_t np, bool lineage) { return lds_bytes(np, lineage); }
 
 }  // namespace
 

@@ -185,12 +185,21 @@ __device__ __forceinline__ float patch_loglik(const float s[5], int u0, int v0, 
     }
     float acc = 0.f;
     if (SRC == kFromTile || SRC == kFromTileInside) {
-        // every LDS read of the patch is issued before the first product
+        // every LDS read of the patch is issued before the first product.  Each
+        // row gets its own base register (the empty asm hides that rows are a
+        // constant apart), so the reads of a row pair up into ds_read2 with
+        // small offsets instead of one address add per pair.  This needs the
+        // tile at the start of the LDS block.
         float z[P * P];
+        typedef __attribute__((address_space(3))) const float lds_f32;
+        lds_f32 *base = (lds_f32 *)pix;
 #pragma unroll
-        for (int jv = 0; jv < P; ++jv)
+        for (int jv = 0; jv < P; ++jv) {
+            lds_f32 *row = base + jv * pitch;
+            __asm__("" : "+v"(row));
 #pragma unroll
-            for (int ju = 0; ju < P; ++ju) z[jv * P + ju] = pix[jv * pitch + ju];
+            for (int ju = 0; ju < P; ++ju) z[jv * P + ju] = row[ju];
+        }
 #pragma unroll
         for (int jv = 0; jv < P; ++jv) {
             float r = 0.f;

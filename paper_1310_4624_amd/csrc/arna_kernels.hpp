@@ -125,33 +125,42 @@ __device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue
     }
 }
 
-// LDS image tile: 64 columns, up to 64 rows; holds z - B, zero outside the
-// image.  The row pitch is 11 mod 32 (and mod 64), so the patch origins of a
-// cluster of particles, which differ by a few rows and columns, fall on
-// different LDS banks.
+// LDS image tile: 64 x 64 pixels of z - B, zero outside the image.  The row
+// pitch is 11 mod 32 (and mod 64), so the patch origins of a cluster of
+// particles, which differ by a few rows and columns, fall on different LDS
+// banks.
 constexpr int kTileCols = 64, kTilePitch = 75, kTileRows = 64;
 constexpr int kMaxWaves = 16;
 
-// Dynamic LDS layout of k_step.
+// Dynamic LDS layout of k_step (the tile comes first: its reads use small
+// immediate offsets from one base register per patch row).
 struct Lds {
+    float *tile;       // [kTileRows][kTilePitch]; later the offspring marks
+    double *wsum;      // [16][6] wave sums (W, W x)
     Prologue *pro;     // 1
-    int *box;          // 4 (+4 pad)
     float *wmax;       // [16] wave maxima
     uint32_t *wq;      // [16][4] wave totals of Q, per slot level
-    double *wsum;      // [16][6] wave sums (W, W x)
     float *st;         // [5][np] propagated particles
-    uint32_t *cq;      // [np] inclusive sums C of the fixed-point weights
-    float *tile;       // [kTileRows][kTilePitch]
+    uint32_t *cq;      // [np] carried weight, then u, then nothing
+    uint16_t *recv;    // [np] receive map
     int32_t *lin;      // [np] (lineage only)
 };
+__host__ __device__ constexpr size_t lds_fixed_bytes() {
+    return (size_t)kTileRows * kTilePitch * sizeof(float) + kMaxWaves * 6 * sizeof(double) + 32 +
+           kMaxWaves * sizeof(float) + kMaxWaves * 4 * sizeof(uint32_t);
+}
+__host__ __device__ constexpr size_t lds_bytes(uint32_t np, bool lineage) {
+    return lds_fixed_bytes() + 5 * (size_t)np * 4 + (size_t)np * 4 + ((size_t)np * 2 + 15) / 16 * 16 +
+           (lineage ? (size_t)np * 4 : 0);
+}
 __device__ __forceinline__ Lds carve(unsigned char *base, uint32_t np) {
     Lds l;
     size_t o = 0;
+    l.tile = (float *)(base + o);
+    o += (size_t)kTileRows * kTilePitch * sizeof(float);
     l.wsum = (double *)(base + o);
     o += kMaxWaves * 6 * sizeof(double);
     l.pro = (Prologue *)(base + o);
-    o += 32;
-    l.box = (int *)(base + o);
     o += 32;
     l.wmax = (float *)(base + o);
     o += kMaxWaves * sizeof(float);
@@ -161,14 +170,10 @@ __device__ __forceinline__ Lds carve(unsigned char *base, uint32_t np) {
     o += 5 * (size_t)np * sizeof(float);
     l.cq = (uint32_t *)(base + o);
     o += (size_t)np * sizeof(uint32_t);
-    l.tile = (float *)(base + o);
-    o += (size_t)kTileRows * kTilePitch * sizeof(float);
+    l.recv = (uint16_t *)(base + o);
+    o += ((size_t)np * 2 + 15) / 16 * 16;
     l.lin = (int32_t *)(base + o);
     return l;
-}
-__host__ __device__ constexpr size_t lds_fixed_bytes() {
-    return kMaxWaves * 6 * sizeof(double) + 32 + 32 + kMaxWaves * sizeof(float) +
-           kMaxWaves * 4 * sizeof(uint32_t) + (size_t)kTileRows * kTilePitch * sizeof(float);
 }
 
 // Step 7 building blocks, shared by k_step and the debug entry point.
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     const uint32_t tid = threadIdx.x, B = blockDim.x;
     const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, nwaves = B / kWave;
     Lds L = carve(smem, np);
-    uint16_t *recv = (uint16_t *)L.tile;   // receive map; the tile is loaded later
+    uint16_t *recv = L.recv;
     const uint32_t pe_base = blockIdx.x * np;   // (f M + m) N_p
     const DebugBufs *D = a.dbg;
     const int32_t *lin_in = D ? D->lin[a.lin_in] : nullptr;
@@ -268,14 +273,13 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
 
     // ---- phase 0: wave 0 redoes the master step of iteration k-1 (steps
     // 1-2); every thread issues the loads of its own slots (most slots keep
-    // their particle) and draws the step-5 normals while they are in flight.
-    if (tid < kWave) prologue_wave(a, f, m, L.pro);
-    if (tid == 0) {
-        L.box[0] = INT_MAX;
-        L.box[1] = INT_MIN;
-        L.box[2] = INT_MAX;
-        L.box[3] = INT_MIN;
-    }
+    // their particle) and of its part of the image tile, and the other waves
+    // draw the step-5 normals, those of wave 0's slots included (parked in
+    // the LDS particle stage, which is free until phase 1).  The
+    // tile is centred where this PE's estimate of k-1 moves in one step
+    // (x + v); a particle whose patch does not fit in it reads the frame,
+    // with the same arithmetic.
+    if (wave == 0) prologue_wave(a, f, m, L.pro);
     uint32_t own[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -286,6 +290,20 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
             own[q] = a.ain[pe_base + s];
         }
     }
+    int tx0 = 0, ty0 = 0;
+    bool tile_on = false, tile_inside = false;
+    if (!POINT) {
+        const double *xh = a.rin[blockIdx.x].xhat;
+        const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
+        if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
+            tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
+            ty0 = (int)floor(cy + 0.5) - kTileRows / 2;
+            tile_on = tx0 < (int)a.lik.W && tx0 + kTileCols > 0 && ty0 < (int)a.lik.H &&
+                      ty0 + kTileRows > 0;
+            tile_inside = tx0 >= 0 && ty0 >= 0 && tx0 + kTileCols <= (int)a.lik.W &&
+                          ty0 + kTileRows <= (int)a.lik.H;
+        }
+    }
     float x[PPT][5];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -294,14 +312,64 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pe_base + own[q]];
     }
-    float e[PPT][5];
+    // Tile pixel i = r kTileCols + c is image pixel (tx0 + c, ty0 + r).  Its
+    // first kTileRegs B pixels are loaded into registers now and written to
+    // LDS at the end of the phase, so the loads overlap the other work.
+    constexpr int kTileRegs = (kTileRows * kTileCols) / 1024;
+    float tv[kTileRegs];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = tid + q * B;
-        if (s < np)
-            five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e[q]);
+    for (int i = 0; i < kTileRegs; ++i) {
+        const uint32_t idx = tid + (uint32_t)i * B;
+        const int u = tx0 + (int)(idx % kTileCols), v = ty0 + (int)(idx / kTileCols);
+        const bool in = tile_on && (unsigned)u < (unsigned)a.lik.W && (unsigned)v < (unsigned)a.lik.H;
+        tv[i] = in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
     }
-    __syncthreads();   // barrier 1: prologue visible, receive map cleared
+    float e[PPT][5];
+    const bool helpers = nwaves > 1;   // other waves draw wave 0's normals
+    if (helpers && tid >= kWave && tid < kWave * (PPT + 1)) {
+        // wave 0's slot of lane j % 64 at level j / 64
+        const uint32_t j = tid - kWave;
+        const uint32_t s = j % kWave + (j / kWave) * B;
+        if (s < np) {
+            float t[5];
+            five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), t);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) L.st[c * np + s] = t[c];
+        }
+    }
+    if (wave != 0 || !helpers) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t s = tid + q * B;
+            if (s < np)
+                five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e[q]);
+        }
+    }
+    if (tile_on) {
+#pragma unroll
+        for (int i = 0; i < kTileRegs; ++i) {
+            const uint32_t idx = tid + (uint32_t)i * B;
+            L.tile[(idx / kTileCols) * kTilePitch + idx % kTileCols] = tv[i];
+        }
+        // the rest of the tile, only when B < 1024
+        for (uint32_t idx = tid + kTileRegs * B; idx < (uint32_t)(kTileRows * kTileCols); idx += B) {
+            const int u = tx0 + (int)(idx % kTileCols), v = ty0 + (int)(idx / kTileCols);
+            const bool in = (unsigned)u < (unsigned)a.lik.W && (unsigned)v < (unsigned)a.lik.H;
+            L.tile[(idx / kTileCols) * kTilePitch + idx % kTileCols] =
+                in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
+        }
+    }
+    __syncthreads();   // barrier 1: prologue, tile and wave 0's normals visible,
+                       // receive map cleared
+    if (helpers && wave == 0) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t s = tid + q * B;
+            if (s < np)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) e[q][c] = L.st[c * np + s];
+        }
+    }
     const Prologue p = *L.pro;
     if (p.nex) {
         build_receive_map(recv, p, np);
@@ -309,8 +377,8 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     }
 
     // ---- phase 1 (steps 3-5 P): received slots are refetched from pred(m);
-    // propagate; stage in LDS; bounding box of the patch origins.
-    int bx0 = INT_MAX, bx1 = INT_MIN, by0 = INT_MAX, by1 = INT_MIN;
+    // propagate; stage in LDS.  A thread reads back only its own slots, so
+    // the likelihood follows without a barrier.
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const uint32_t s = tid + q * B;
@@ -338,52 +406,6 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
             a.pout[c * N + pe_base + s] = x[q][c];
         }
         L.cq[s] = __float_as_uint(lam);   // parked until the likelihood is known
-        if (!POINT) {
-            int u0, v0;
-            if (patch_origin<HALF>(x[q][0], x[q][1], a.lik.W, a.lik.H, u0, v0)) {
-                bx0 = min(bx0, u0);
-                bx1 = max(bx1, u0);
-                by0 = min(by0, v0);
-                by1 = max(by1, v0);
-            }
-        }
-    }
-    bool use_tile = false, tile_inside = false;
-    int tx0 = 0, ty0 = 0;
-    if (!POINT) {
-        bx0 = wave_min_i32(bx0);
-        bx1 = wave_max_i32(bx1);
-        by0 = wave_min_i32(by0);
-        by1 = wave_max_i32(by1);
-        if (lane == 0 && bx0 <= bx1) {
-            atomicMin(&L.box[0], bx0);
-            atomicMax(&L.box[1], bx1);
-            atomicMin(&L.box[2], by0);
-            atomicMax(&L.box[3], by1);
-        }
-        __syncthreads();   // barrier 2: bounding box (receive map no longer read)
-        tx0 = L.box[0];
-        ty0 = L.box[2];
-        int th = 0;
-        if (tx0 <= L.box[1]) {   // at least one patch touches the image
-            const int tw = L.box[1] - tx0 + P;
-            th = L.box[3] - ty0 + P;
-            use_tile = tw <= kTileCols && th <= kTileRows;
-            tile_inside = tx0 >= 0 && ty0 >= 0 && tx0 + tw <= a.lik.W && ty0 + th <= a.lik.H;
-        }
-        if (use_tile) {
-            // tile pixel (r, c) is image pixel (tx0 + c, ty0 + r)
-            for (int idx = (int)tid; idx < th * kTileCols; idx += (int)B) {
-                const int r = idx / kTileCols, c = idx % kTileCols;
-                const int u = tx0 + c, v = ty0 + r;
-                const bool in = (unsigned)u < (unsigned)a.lik.W && (unsigned)v < (unsigned)a.lik.H;
-                L.tile[r * kTilePitch + c] =
-                    in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
-            }
-            __syncthreads();   // barrier 3: tile
-        }
-    } else {
-        __syncthreads();   // barrier 2: LDS staging complete
     }
 
     // ---- phase 2 (step 5 U): log-likelihood of every slot; u = lambda + l,
@@ -397,20 +419,24 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         float xs[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) xs[c] = L.st[c * np + s];
-        float ell;
+        float ell = 0.f;
+        int u0, v0;
         if (POINT) {
             ell = loglik_point(xs, a.lik, f);
-        } else if (use_tile) {
-            int u0, v0;
-            ell = 0.f;
-            if (patch_origin<HALF>(xs[0], xs[1], a.lik.W, a.lik.H, u0, v0)) {
-                const float *pix = L.tile + (v0 - ty0) * kTilePitch + (u0 - tx0);
+        } else if (patch_origin<HALF>(xs[0], xs[1], a.lik.W, a.lik.H, u0, v0)) {
+            const int du = u0 - tx0, dv = v0 - ty0;
+            if (tile_on && (unsigned)du <= (unsigned)(kTileCols - P) &&
+                (unsigned)dv <= (unsigned)(kTileRows - P)) {
+                const float *pix = L.tile + dv * kTilePitch + du;
                 ell = tile_inside
                           ? patch_loglik<HALF, kFromTileInside>(xs, u0, v0, pix, kTilePitch, a.lik)
                           : patch_loglik<HALF, kFromTile>(xs, u0, v0, pix, kTilePitch, a.lik);
+            } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W && v0 + P <= (int)a.lik.H) {
+                ell = patch_loglik<HALF, kFromImage>(xs, u0, v0,
+                                                     a.lik.img + (size_t)v0 * a.lik.W + u0, 0, a.lik);
+            } else {
+                ell = patch_loglik<HALF, kFromImageBorder>(xs, u0, v0, a.lik.img, 0, a.lik);
             }
-        } else {
-            ell = loglik_patch<HALF>(xs, a.lik);
         }
         bad |= (ell != ell);
         const float uu = __uint_as_float(L.cq[s]) + ell;
@@ -425,7 +451,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
-    __syncthreads();   // barrier 4: wave maxima
+    __syncthreads();   // barrier 4: wave maxima (tile reads done)
     float lstar = L.wmax[0];
     for (uint32_t w = 1; w < nwaves; ++w) lstar = fmaxf(lstar, L.wmax[w]);
 
@@ -541,8 +567,19 @@ __global__ void k_init(float *st, uint16_t *anc, pf_pe_record *rec, int32_t *lin
                        uint32_t infoshare, uint32_t key0, uint32_t key1, uint32_t FM) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < FM) {
+        // PE records of step 0: equal masses; x^m is the mean of the initial
+        // cloud (the truth, or the centre of the uniform prior), which also
+        // places the first step's image tile.
+        const uint32_t pf = (uint32_t)g / M, pm = (uint32_t)g % M;
+        const float *t = truth + 5 * pf;
         pf_pe_record r = {};
         r.log_mass = 0.0;
+        const bool prior = infoshare && pm != 0;
+        r.xhat[0] = prior ? 0.5 * ((double)W - 1.0) : (double)t[0];
+        r.xhat[1] = prior ? 0.5 * ((double)H - 1.0) : (double)t[1];
+        r.xhat[2] = prior ? 0.0 : (double)t[2];
+        r.xhat[3] = prior ? 0.0 : (double)t[3];
+        r.xhat[4] = (double)t[4];
         rec[g] = r;
     }
     if (g >= N) return;
