@@ -710,3 +710,298 @@ double orc_loglik(const orc_config *c, const float *frame, uint32_t f, const dou
     particle p = {st[0], st[1], st[2], st[3], st[4]};
     return log_likelihood(c, frame, f, p);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of the log marginal likelihood with the discrete choices frozen */
+/* ------------------------------------------------------------------------ */
+/* For a run of K iterations the filter's estimate of log p(z_1..z_K) is, per
+ * filter, J = sum_k (log W_k - log N_p), W_k = sum_m W^(m)_k of step 9 (the
+ * carried weights are renormalized by W_{k-1} in step 4, so the increments
+ * chain).  Hold every discrete choice of the run fixed -- ring, N_ex, the
+ * exchanged slots, the ancestors of step 7 and the patch centres of the
+ * likelihood -- and the normals fixed by their Philox counters; J is then a
+ * smooth function of theta = (psf_sigma, I0, q), where I0 shifts the
+ * intensity of every particle of the starting state.
+ *
+ * orc_grad runs K iterations exactly as orc_step does (so its choices are
+ * the filter's own) and carries alongside every particle its derivative
+ * d(particle)/d(theta), and alongside every PE d(log W^(m))/d(theta): forward
+ * differentiation of each step by the chain rule.  It can record the choices
+ * (a tape); orc_replay evaluates J at another theta with those choices, which
+ * is what finite differences of the frozen objective need.
+ *
+ * Both run from the filter's start (orc_create) over K frames stored one
+ * after another.  Patch likelihood only. */
+
+#define NTH 3   /* theta = (psf_sigma, I0, q) */
+
+typedef struct {
+    particle p;
+    double d[5][NTH];   /* d(x, y, vx, vy, I) / d(theta) */
+} dual_particle;
+
+/* Patch log-likelihood with a fixed centre (cx, cy) and its partial
+ * derivatives in x, y, I and psf_sigma.  The value is computed exactly as
+ * log_likelihood does; per pixel, with r0 = z - B and g the PSF,
+ *   l_pix = (r0^2 - (r0 - I g)^2) / (2 s_n^2),
+ *   dl_pix/dg = I (r0 - I g) / s_n^2,   dl_pix/dI = g (r0 - I g) / s_n^2,
+ *   dg/dx = g (u - x) / s^2,  dg/dy = g (v - y) / s^2,
+ *   dg/ds = g ((u - x)^2 + (v - y)^2) / s^3. */
+static double loglik_centred(const orc_config *c, double psf_sigma, const float *frame,
+                             long cx, long cy, particle p, double grad[4])
+{
+    double s2 = c->noise_sigma * c->noise_sigma;
+    double ps2 = psf_sigma * psf_sigma;
+    int half = (int)c->patch / 2;
+    double l = 0.0;
+    grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
+    for (long v = cy - half; v <= cy + half; ++v) {
+        if (v < 0 || v >= (long)c->height) continue;
+        for (long u = cx - half; u <= cx + half; ++u) {
+            if (u < 0 || u >= (long)c->width) continue;
+            double dx = (double)u - p.x, dy = (double)v - p.y;
+            double g = exp(-(dx * dx + dy * dy) / (2.0 * ps2));
+            double z = (double)frame[(size_t)v * c->width + u];
+            double r0 = z - c->background;
+            double r1 = r0 - p.I * g;
+            l += (r0 * r0 - r1 * r1) / (2.0 * s2);
+            double dl_dg = p.I * r1 / s2;
+            grad[0] += dl_dg * g * dx / ps2;
+            grad[1] += dl_dg * g * dy / ps2;
+            grad[2] += g * r1 / s2;
+            grad[3] += dl_dg * g * (dx * dx + dy * dy) / (ps2 * psf_sigma);
+        }
+    }
+    return l;
+}
+
+/* The patch centre of log_likelihood, or 0 when the patch misses the image. */
+static int patch_centre(const orc_config *c, particle p, int32_t *cx, int32_t *cy)
+{
+    int half = (int)c->patch / 2;
+    double fx = floor(p.x + 0.5), fy = floor(p.y + 0.5);
+    if (!(fx >= -half && fx <= (double)c->width - 1 + half)) return 0;
+    if (!(fy >= -half && fy <= (double)c->height - 1 + half)) return 0;
+    *cx = (int32_t)fx;
+    *cy = (int32_t)fy;
+    return 1;
+}
+
+/* One run.  record != 0: choices computed as in orc_step and written to the
+ * tape (each tape pointer may be NULL); record == 0: choices read from the
+ * tape.  dJ (nullable) receives dJ/dtheta. */
+static int run_frozen(const orc_config *cfg, const double *truth, double dI0,
+                      const float *frames, uint32_t K, int record,
+                      uint32_t *tape_nex, uint32_t *tape_anc, int32_t *tape_centre,
+                      double *J, double *dJ)
+{
+    if (cfg->lik_mode != ORC_LIK_PATCH) return -6;
+    const uint32_t F = cfg->n_filters, M = cfg->n_pe, np = cfg->n_per_pe;
+    const size_t N = n_total(cfg), frame_size = (size_t)cfg->width * cfg->height;
+    const uint32_t qmax = orc_qmax(np);
+    const double sq = sqrt(cfg->q), dsq = 0.5 / sq;   /* sqrt(q) and its q-derivative */
+    int status = 0;
+
+    orc_filter *o = orc_create(cfg, truth);
+    if (!o) return -1;
+    dual_particle *s = (dual_particle *)calloc(N, sizeof(dual_particle));
+    dual_particle *src = (dual_particle *)malloc(sizeof(dual_particle) * N);
+    dual_particle *prop = (dual_particle *)malloc(sizeof(dual_particle) * N);
+    double *lam = (double *)malloc(sizeof(double) * N);
+    double *dlam = (double *)malloc(sizeof(double) * N * NTH);
+    double *ell = (double *)malloc(sizeof(double) * N);
+    double *dell = (double *)malloc(sizeof(double) * N * NTH);
+    double *L = (double *)calloc((size_t)F * M, sizeof(double));
+    double *dL = (double *)calloc((size_t)F * M * NTH, sizeof(double));
+    double *Lnew = (double *)malloc(sizeof(double) * F * M);
+    double *dLnew = (double *)malloc(sizeof(double) * F * M * NTH);
+    uint32_t *pred = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    uint32_t *pi = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    uint32_t *coff = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    uint32_t *P = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    uint32_t *origin_pe = (uint32_t *)malloc(sizeof(uint32_t) * N);
+    for (size_t g = 0; g < N; ++g) {
+        s[g].p = o->s[g];
+        s[g].p.I += dI0;
+        s[g].d[4][1] = 1.0;          /* dI/dI0 */
+    }
+    for (uint32_t f = 0; f < F; ++f) {
+        J[f] = 0.0;
+        if (dJ) for (int j = 0; j < NTH; ++j) dJ[f * NTH + j] = 0.0;
+    }
+
+    for (uint32_t k = 1; k <= K; ++k) {
+        const float *frame = frames + (size_t)(k - 1) * frame_size;
+        /* steps 1-4: ring, N_ex, exchange, renormalized carried weights */
+        for (uint32_t f = 0; f < F; ++f) {
+            const double *Lf = L + (size_t)f * M;
+            const double *dLf = dL + (size_t)f * M * NTH;
+            orc_ring(cfg->seed, f, k, M, cfg->mode, pi, pred, NULL);
+            uint32_t nex;
+            if (record) {
+                pe_masses(Lf, M, P);
+                nex = orc_nex(P, M, np, cfg->mode, cfg->fixed_ratio, cfg->initial_ratio,
+                              cfg->eff_cutoff, k == 1);
+                if (tape_nex) tape_nex[(size_t)(k - 1) * F + f] = nex;
+            } else {
+                nex = tape_nex[(size_t)(k - 1) * F + f];
+            }
+            for (uint32_t m = 0; m < M; ++m) coff[m] = orc_exchange_offset(cfg->seed, f, k, m, np);
+            size_t base = (size_t)f * M * np;
+            for (uint32_t m = 0; m < M; ++m)
+                for (uint32_t t = 0; t < np; ++t) {
+                    src[base + (size_t)m * np + t] = s[base + (size_t)m * np + t];
+                    origin_pe[base + (size_t)m * np + t] = m;
+                }
+            if (M > 1 && nex > 0)
+                for (uint32_t m = 0; m < M; ++m)
+                    for (uint32_t t = 0; t < nex; ++t) {
+                        size_t g = base + (size_t)m * np + orc_selected_slot(t, coff[m], np, nex);
+                        size_t gs = base + (size_t)pred[m] * np +
+                                    orc_selected_slot(t, coff[pred[m]], np, nex);
+                        src[g] = s[gs];
+                        origin_pe[g] = pred[m];
+                    }
+            /* lambda = L_origin - log sum_m W_m; its derivative subtracts the
+             * mass-weighted mean of dL */
+            double Lg = logsumexp(Lf, M);
+            double mean_dL[NTH] = {0, 0, 0};
+            for (uint32_t m = 0; m < M; ++m) {
+                double pm = (Lg == -INFINITY) ? 0.0 : exp(Lf[m] - Lg);
+                for (int j = 0; j < NTH; ++j) mean_dL[j] += pm * dLf[m * NTH + j];
+            }
+            for (size_t i = base; i < base + (size_t)M * np; ++i) {
+                lam[i] = Lf[origin_pe[i]] - Lg;
+                for (int j = 0; j < NTH; ++j)
+                    dlam[i * NTH + j] = dLf[origin_pe[i] * NTH + j] - mean_dL[j];
+            }
+        }
+
+        /* steps 5-8 per PE */
+        #pragma omp parallel for schedule(static)
+        for (long fm = 0; fm < (long)F * M; ++fm) {
+            uint32_t f = (uint32_t)(fm / M), m = (uint32_t)(fm % M);
+            size_t base = (size_t)fm * np;
+            for (uint32_t t = 0; t < np; ++t) {
+                size_t g = base + t;
+                uint32_t r[4];
+                double eps[5];
+                draw(cfg->seed, TAG_PROP, 0, m * np + t, k, f, r);
+                five_normals(r, eps);
+                dual_particle *a = &src[g], *b = &prop[g];
+                b->p = propagate(a->p, eps, cfg->q, cfg->sigma_I);
+                /* tangent of the NCV step: position += velocity, and the
+                 * noise scales with sqrt(q) */
+                for (int j = 0; j < NTH; ++j) {
+                    double nq = (j == 2) ? dsq : 0.0;
+                    b->d[0][j] = a->d[0][j] + a->d[2][j] + nq * eps[0] / sqrt(3.0);
+                    b->d[2][j] = a->d[2][j] + nq * (sqrt(3.0) / 2.0 * eps[0] + 0.5 * eps[1]);
+                    b->d[1][j] = a->d[1][j] + a->d[3][j] + nq * eps[2] / sqrt(3.0);
+                    b->d[3][j] = a->d[3][j] + nq * (sqrt(3.0) / 2.0 * eps[2] + 0.5 * eps[3]);
+                    b->d[4][j] = a->d[4][j];
+                }
+                int32_t cx = 0, cy = 0;
+                int has;
+                int32_t *tc = tape_centre ? tape_centre + ((size_t)(k - 1) * N + g) * 2 : NULL;
+                if (record) {
+                    has = patch_centre(cfg, b->p, &cx, &cy);
+                    if (tc) { tc[0] = has ? cx : INT32_MIN; tc[1] = has ? cy : INT32_MIN; }
+                } else {
+                    has = tc[0] != INT32_MIN;
+                    cx = tc[0];
+                    cy = tc[1];
+                }
+                double gr[4] = {0, 0, 0, 0};
+                ell[g] = has ? loglik_centred(cfg, cfg->psf_sigma, frame, cx, cy, b->p, gr) : 0.0;
+                for (int j = 0; j < NTH; ++j)
+                    dell[g * NTH + j] = gr[0] * b->d[0][j] + gr[1] * b->d[1][j] +
+                                        gr[2] * b->d[4][j] + (j == 0 ? gr[3] : 0.0);
+            }
+            /* step 6 and the derivative of log W^(m) = log sum exp(u) */
+            double lstar = -INFINITY;
+            for (uint32_t t = 0; t < np; ++t) {
+                double u = lam[base + t] + ell[base + t];
+                if (u > lstar) lstar = u;
+            }
+            double *w = (double *)malloc(sizeof(double) * np);
+            double wsum = 0.0, dsum[NTH] = {0, 0, 0};
+            for (uint32_t t = 0; t < np; ++t) {
+                w[t] = (lstar == -INFINITY) ? 1.0 : exp(lam[base + t] + ell[base + t] - lstar);
+                wsum += w[t];
+                for (int j = 0; j < NTH; ++j)
+                    dsum[j] += w[t] * (dlam[(base + t) * NTH + j] + dell[(base + t) * NTH + j]);
+            }
+            Lnew[fm] = (lstar == -INFINITY) ? -INFINITY : lstar + log(wsum);
+            for (int j = 0; j < NTH; ++j) dLnew[fm * NTH + j] = dsum[j] / wsum;
+            /* step 7: ancestors (computed as in orc_step, or from the tape) */
+            uint32_t *anc = (uint32_t *)malloc(sizeof(uint32_t) * np);
+            uint32_t *ta = tape_anc ? tape_anc + (size_t)(k - 1) * N + base : NULL;
+            if (record) {
+                uint32_t *Q = (uint32_t *)malloc(sizeof(uint32_t) * np);
+                uint64_t T = 0;
+                for (uint32_t t = 0; t < np; ++t) {
+                    double qd = floor(w[t] * (double)qmax);
+                    if (!(qd >= 0.0)) qd = 0.0;
+                    if (qd > (double)qmax) qd = (double)qmax;
+                    Q[t] = (uint32_t)qd;
+                    T += Q[t];
+                }
+                if (T > 0 && T <= 0xFFFFFFFFull) {
+                    orc_resample(Q, np, orc_resample_offset(cfg->seed, f, k, m, (uint32_t)T), anc);
+                } else {
+                    for (uint32_t t = 0; t < np; ++t) anc[t] = t;
+                    #pragma omp atomic write
+                    status = -4;
+                }
+                if (ta) memcpy(ta, anc, sizeof(uint32_t) * np);
+                free(Q);
+            } else {
+                memcpy(anc, ta, sizeof(uint32_t) * np);
+            }
+            /* step 8 */
+            for (uint32_t t = 0; t < np; ++t) s[base + t] = prop[base + anc[t]];
+            free(anc);
+            free(w);
+        }
+
+        /* steps 9-10: J += log W_k - log N_p and its derivative */
+        for (uint32_t f = 0; f < F; ++f) {
+            const double *Lf = Lnew + (size_t)f * M;
+            double Lg = logsumexp(Lf, M);
+            J[f] += Lg - log((double)np);
+            if (dJ)
+                for (uint32_t m = 0; m < M; ++m) {
+                    double pm = (Lg == -INFINITY) ? 0.0 : exp(Lf[m] - Lg);
+                    for (int j = 0; j < NTH; ++j)
+                        dJ[f * NTH + j] += pm * dLnew[((size_t)f * M + m) * NTH + j];
+                }
+        }
+        memcpy(L, Lnew, sizeof(double) * F * M);
+        memcpy(dL, dLnew, sizeof(double) * F * M * NTH);
+    }
+
+    orc_destroy(o);
+    free(s); free(src); free(prop); free(lam); free(dlam); free(ell); free(dell);
+    free(L); free(dL); free(Lnew); free(dLnew); free(pred); free(pi); free(coff); free(P);
+    free(origin_pe);
+    return status;
+}
+
+/* J and dJ/dtheta at the configuration's theta; the choices may be recorded
+ * ([K][F], [K][N], [K][N][2]; each pointer nullable). */
+int orc_grad(const orc_config *cfg, const double *truth, const float *frames, uint32_t K,
+             double *J, double *dJ, uint32_t *tape_nex, uint32_t *tape_anc, int32_t *tape_centre)
+{
+    return run_frozen(cfg, truth, 0.0, frames, K, 1, tape_nex, tape_anc, tape_centre, J, dJ);
+}
+
+/* J with the choices of a tape, at cfg's psf_sigma and q, and every starting
+ * intensity shifted by dI0. */
+int orc_replay(const orc_config *cfg, const double *truth, double dI0, const float *frames,
+               uint32_t K, const uint32_t *tape_nex, const uint32_t *tape_anc,
+               const int32_t *tape_centre, double *J)
+{
+    if (!tape_nex || !tape_anc || !tape_centre) return -1;
+    return run_frozen(cfg, truth, dI0, frames, K, 0, (uint32_t *)tape_nex, (uint32_t *)tape_anc,
+                      (int32_t *)tape_centre, J, NULL);
+}

@@ -119,6 +119,13 @@ def _declare(L):
     L.orc_propagate.argtypes = [PD, PD, ctypes.c_double, ctypes.c_double, PD]
     L.orc_loglik.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_float), u32, PD]
     L.orc_loglik.restype = ctypes.c_double
+    PI32 = ctypes.POINTER(ctypes.c_int32)
+    PF = ctypes.POINTER(ctypes.c_float)
+    L.orc_grad.argtypes = [ctypes.POINTER(_Config), PD, PF, u32, PD, PD, P32, P32, PI32]
+    L.orc_grad.restype = i32
+    L.orc_replay.argtypes = [ctypes.POINTER(_Config), PD, ctypes.c_double, PF, u32, P32, P32,
+                             PI32, PD]
+    L.orc_replay.restype = i32
 
 
 def _p(a, ct):
@@ -241,12 +248,14 @@ class OracleConfig:
         names = {f for f in cls.__dataclass_fields__ if f != "extra"}
         return cls(**{k: v for k, v in d.items() if k in names})
 
-    def to_c(self) -> _Config:
+    def to_c(self, psf_sigma: float | None = None, q: float | None = None) -> _Config:
+        """psf_sigma / q, when given, are passed unrounded (finite differences)."""
         return _Config(self.n_filters, self.n_pe, self.n_per_pe, self.width, self.height,
                        self.patch, self.mode, self.init_mode, self.lik_mode,
                        _f32(self.fixed_ratio), _f32(self.initial_ratio), _f32(self.eff_cutoff),
-                       _f32(self.psf_sigma), _f32(self.background), _f32(self.noise_sigma),
-                       _f32(self.q), _f32(self.sigma_I), self.seed)
+                       _f32(self.psf_sigma) if psf_sigma is None else float(psf_sigma),
+                       _f32(self.background), _f32(self.noise_sigma),
+                       _f32(self.q) if q is None else float(q), _f32(self.sigma_I), self.seed)
 
     @property
     def N(self) -> int:
@@ -318,3 +327,60 @@ class Oracle:
         rc = lib().orc_step(self._h, _p(fr, ctypes.c_float), ctypes.byref(tr) if trace else None)
         out["status"] = int(rc)
         return out
+
+
+# ------------------------------------------------------------------ gradient
+@dataclass
+class Tape:
+    """Discrete choices of a run: N_ex [K][F], ancestors [K][N], patch
+    centres [K][N][2] (INT32_MIN where a patch misses the image)."""
+    n_ex: np.ndarray
+    anc: np.ndarray
+    centre: np.ndarray
+
+
+def _frames_k(frames) -> tuple:
+    fr = np.ascontiguousarray(frames, dtype=np.float32)
+    return fr, fr.shape[0]
+
+
+def grad(cfg, truth, frames):
+    """Run K = len(frames) iterations from the start; return J [F] (the
+    estimate of log p(z_1..z_K) per filter), dJ/dtheta [F][3] with
+    theta = (psf_sigma, I0, q) and the discrete choices held fixed, and the
+    tape of those choices."""
+    if isinstance(cfg, dict):
+        cfg = OracleConfig.from_dict(cfg)
+    c = cfg.to_c()
+    fr, K = _frames_k(frames)
+    t = np.ascontiguousarray(truth, dtype=np.float64)
+    F, N = cfg.n_filters, cfg.N
+    J = np.zeros(F)
+    dJ = np.zeros((F, 3))
+    tape = Tape(np.zeros((K, F), np.uint32), np.zeros((K, N), np.uint32),
+                np.zeros((K, N, 2), np.int32))
+    rc = lib().orc_grad(ctypes.byref(c), _p(t, ctypes.c_double), _p(fr, ctypes.c_float), K,
+                        _p(J, ctypes.c_double), _p(dJ, ctypes.c_double),
+                        _p(tape.n_ex, ctypes.c_uint32), _p(tape.anc, ctypes.c_uint32),
+                        _p(tape.centre, ctypes.c_int32))
+    if rc != 0:
+        raise RuntimeError(f"orc_grad failed ({rc})")
+    return J, dJ, tape
+
+
+def replay(cfg, truth, frames, tape: Tape, psf_sigma=None, q=None, dI0: float = 0.0):
+    """J [F] with the choices of `tape`; psf_sigma and q unrounded when given,
+    every starting intensity shifted by dI0."""
+    if isinstance(cfg, dict):
+        cfg = OracleConfig.from_dict(cfg)
+    c = cfg.to_c(psf_sigma=psf_sigma, q=q)
+    fr, K = _frames_k(frames)
+    t = np.ascontiguousarray(truth, dtype=np.float64)
+    J = np.zeros(cfg.n_filters)
+    rc = lib().orc_replay(ctypes.byref(c), _p(t, ctypes.c_double), float(dI0),
+                          _p(fr, ctypes.c_float), K, _p(tape.n_ex, ctypes.c_uint32),
+                          _p(tape.anc, ctypes.c_uint32), _p(tape.centre, ctypes.c_int32),
+                          _p(J, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"orc_replay failed ({rc})")
+    return J
