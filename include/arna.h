@@ -140,6 +140,38 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map);
  * if any iteration so far produced a NaN log-weight (the flag is sticky). */
 int pf_estimate(pf_ctx *c, pf_estimate_t *out);
 
+/* ------------------------------------------------------------- gradient */
+/* The filter's estimate of the log marginal likelihood of a run of K
+ * iterations is, per filter, J = sum_k (log W_k - log N_p), with W_k the sum
+ * of the PE masses of Alg. 3 step 9 (the carried weights are renormalized by
+ * W_{k-1} in step 4, so the increments chain).  With every discrete choice of
+ * the run held fixed -- ring, N_ex, exchanged slots, the ancestors of step 7
+ * and the patch positions of the likelihood -- and the normals fixed by their
+ * counters, J is a smooth function of theta = (psf_sigma, I0, q); I0 shifts
+ * the intensity of every particle of the state the recording starts from
+ * (for a recording that starts at pf_init with the tracking start, that is
+ * the true initial intensity).
+ *
+ * pf_grad_begin starts recording: the next max_steps iterations (pf_step /
+ * pf_run) keep their propagated particles, ancestors and PE records on the
+ * device ((max_steps + 1) x (22 N + 56 F M) bytes, kept for reuse until
+ * pf_destroy).  Patch likelihood only (PF_EUNSUPPORTED otherwise); q must be
+ * positive (PF_EINVAL).  PF_ESTATE while recording or after pf_exchange.
+ * An iteration beyond max_steps returns PF_ESTATE and does nothing. */
+int pf_grad_begin(pf_ctx *c, uint32_t max_steps);
+
+/* While recording: host_J (host double [F]) receives J over the iterations
+ * recorded so far.  Synchronizes the stream.  PF_ESTATE if not recording. */
+int pf_grad_value(pf_ctx *c, double *host_J);
+
+/* Run the reverse sweep over the recorded iterations and stop recording.
+ * d_frames: the recorded iterations' frames again, d_frames + i * frame_stride
+ * for the i-th recorded iteration (device float32, caller-owned).
+ * host_out (host double [F][4]) receives per filter (J, dJ/dpsf_sigma,
+ * dJ/dI0, dJ/dq).  Synchronizes the stream; the context then continues from
+ * the last recorded iteration.  PF_ESTATE if not recording. */
+int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double *host_out);
+
 /* Free everything the context owns (synchronizes its stream first). */
 void pf_destroy(pf_ctx *c);
 
@@ -175,6 +207,14 @@ int pf_debug_set_state(pf_ctx *c, const float *host_state, const double *host_lo
                        uint64_t step);
 /* Set the lineage tags (host int32 [N]); needs PF_DEBUG_LINEAGE. */
 int pf_debug_set_lineage(pf_ctx *c, const int32_t *host_tags);
+
+/* Replay of another run's discrete choices (test support): the next iteration
+ * takes its ancestors from d_anc (device uint32 [N], ancestor slot within the
+ * PE, non-decreasing within each PE) instead of step 7, and N_ex from d_nex
+ * (device uint32 [F]) instead of step 2; either may be NULL.  The pointers are
+ * read by that iteration only (they must stay valid until the stream has
+ * passed it) and are then forgotten. */
+int pf_debug_force_next(pf_ctx *c, const uint32_t *d_anc, const uint32_t *d_nex);
 
 /* The device integer stages on host arrays, run synchronously on the current
  * device with the same device code as pf_step. */

@@ -82,10 +82,14 @@ SIGNATURES = {
     "pf_estimate": (ctypes.c_int, [_P, ctypes.POINTER(pf_estimate_t)]),
     "pf_destroy": (None, [_P]),
     "pf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pf_grad_begin": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "pf_grad_end": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
+    "pf_grad_value": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "pf_debug_size": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "pf_debug_get": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t]),
     "pf_debug_set_state": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     "pf_debug_set_lineage": (ctypes.c_int, [_P, _P]),
+    "pf_debug_force_next": (ctypes.c_int, [_P, _P, _P]),
     "pf_debug_resample_q": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "pf_debug_nex": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int,

@@ -27,6 +27,7 @@
 #include "arna.h"
 #include "arna_device.hpp"
 #include "arna_kernels.hpp"
+#include "arna_adjoint.hpp"
 
 using namespace arna;
 
@@ -79,6 +80,20 @@ struct pf_ctx {
     float *t_prop, *t_ell, *t_lam;
     uint64_t step;
     bool exchanged;
+    // gradient recording: while g_cap > 0 the state of iteration g_start + i
+    // lives in slot i of the tape (slot 0: the state at pf_grad_begin)
+    uint32_t g_cap, g_len, g_alloc;
+    uint64_t g_start;
+    uint32_t *g_nex;               // [g_alloc + 1][F] N_ex of each recorded iteration
+    // choices forced on the next iteration (pf_debug_force_next), or NULL
+    const uint32_t *force_anc, *force_nex;
+    float *g_prop;                 // [g_alloc + 1][5][N]
+    uint16_t *g_anc;               // [g_alloc + 1][N]
+    pf_pe_record *g_rec;           // [g_alloc + 1][F M]
+    float *g_bar[2];               // [5][N] adjoints of resampled slots
+    double *g_lbar[2];             // [2][F M]
+    double *g_theta;               // [F M][2]
+    double *g_out;                 // [F][4]
     uint32_t key0, key1, fixed_nex, initial_nex, cutoff_ppm, qmax;
     Dyn dyn;
     Lik lik;
@@ -101,6 +116,17 @@ int dev_alloc(T **p, size_t count) {
         return PF_ENOMEM;
     }
     return PF_OK;
+}
+
+// Buffers of the current iteration (the tape while recording).
+float *cur_prop(pf_ctx *c) {
+    return c->g_cap ? c->g_prop + (size_t)c->g_len * 5 * c->N : c->prop[c->cur];
+}
+uint16_t *cur_anc(pf_ctx *c) {
+    return c->g_cap ? c->g_anc + (size_t)c->g_len * c->N : c->anc[c->cur];
+}
+pf_pe_record *cur_rec(pf_ctx *c) {
+    return c->g_cap ? c->g_rec + (size_t)c->g_len * c->FM : c->rec[c->cur];
 }
 
 template <int PPT, int HALF, bool POINT>
@@ -128,6 +154,33 @@ void *pick_step_kernel(uint32_t ppt, uint32_t half, bool point) {
         ARNA_HALVES(4)
     }
 #undef ARNA_HALVES
+    return nullptr;
+}
+
+template <int PPT, int HALF>
+void *adj_kernel() {
+    return reinterpret_cast<void *>(&k_adjoint<PPT, HALF>);
+}
+
+void *pick_adjoint_kernel(uint32_t ppt, uint32_t half) {
+#define ARNA_ADJ_HALVES(P)                     \
+    switch (half) {                            \
+        case 0: return adj_kernel<P, 0>();     \
+        case 1: return adj_kernel<P, 1>();     \
+        case 2: return adj_kernel<P, 2>();     \
+        case 3: return adj_kernel<P, 3>();     \
+        case 4: return adj_kernel<P, 4>();     \
+        case 5: return adj_kernel<P, 5>();     \
+        case 6: return adj_kernel<P, 6>();     \
+        case 7: return adj_kernel<P, 7>();     \
+        default: return nullptr;               \
+    }
+    if (ppt == 1) {
+        ARNA_ADJ_HALVES(1)
+    } else {
+        ARNA_ADJ_HALVES(4)
+    }
+#undef ARNA_ADJ_HALVES
     return nullptr;
 }
 
@@ -160,20 +213,26 @@ void free_all(pf_ctx *c) {
     void *ptrs[] = {c->prop[0], c->prop[1], c->anc[0], c->anc[1], c->rec[0], c->rec[1],
                     c->lin[0], c->lin[1],
                     c->ring_tab, c->err, c->nex_used, c->est, c->t_pred, c->t_q, c->t_anc,
-                    c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg};
+                    c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
+                    c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
+                    c->g_lbar[1], c->g_theta, c->g_out};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
 
-int ensure_ring(pf_ctx *c, uint64_t k) {
+// Ring table for iteration k; when it has to be rebuilt, the batch of
+// kRingSteps iterations starts at k (forward runs) or ends at k (the adjoint
+// sweep, which runs backwards).
+int ensure_ring(pf_ctx *c, uint64_t k, bool downward = false) {
     if (c->cfg.mode != PF_MODE_ARNA || c->cfg.n_pe <= 1) return PF_OK;
     if (c->ring_valid && k >= c->ring_base && k < c->ring_base + kRingSteps) return PF_OK;
+    const uint64_t base = (downward && k >= kRingSteps) ? k - (kRingSteps - 1) : (downward ? 1 : k);
     const uint32_t M = c->cfg.n_pe;
     hipLaunchKernelGGL(k_ring, dim3(kRingSteps, c->cfg.n_filters), dim3(256),
-                       2 * M * sizeof(uint16_t), c->stream, c->ring_tab, (uint32_t)k,
+                       2 * M * sizeof(uint16_t), c->stream, c->ring_tab, (uint32_t)base,
                        c->cfg.n_filters, M, c->key0, c->key1);
     HIP_OK(hipGetLastError());
-    c->ring_base = k;
+    c->ring_base = base;
     c->ring_valid = true;
     return PF_OK;
 }
@@ -182,12 +241,21 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     StepArgs a;
     memset(&a, 0, sizeof(a));
     const int nxt = 1 - c->cur;
-    a.pin = c->prop[c->cur];
-    a.ain = c->anc[c->cur];
-    a.pout = c->prop[nxt];
-    a.aout = c->anc[nxt];
-    a.rin = c->rec[c->cur];
-    a.rout = c->rec[nxt];
+    a.pin = cur_prop(c);
+    a.ain = cur_anc(c);
+    a.rin = cur_rec(c);
+    a.force_anc = c->force_anc;
+    a.force_nex = c->force_nex;
+    if (c->g_cap) {
+        a.nex_rec = c->g_nex + (size_t)(c->g_len + 1) * c->cfg.n_filters;
+        a.pout = c->g_prop + (size_t)(c->g_len + 1) * 5 * c->N;
+        a.aout = c->g_anc + (size_t)(c->g_len + 1) * c->N;
+        a.rout = c->g_rec + (size_t)(c->g_len + 1) * c->FM;
+    } else {
+        a.pout = c->prop[nxt];
+        a.aout = c->anc[nxt];
+        a.rout = c->rec[nxt];
+    }
     a.ring = (c->cfg.mode == PF_MODE_ARNA && c->cfg.n_pe > 1)
                  ? c->ring_tab + (size_t)(k - c->ring_base) * c->FM
                  : nullptr;
@@ -216,6 +284,7 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
 int launch_step(pf_ctx *c, const float *frame) {
     const uint64_t k = c->step + 1;
     if (k > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
+    if (c->g_cap && c->g_len >= c->g_cap) return PF_ESTATE;   // tape full
     int rc = ensure_ring(c, k);
     if (rc != PF_OK) return rc;
     StepArgs a = make_args(c, k, frame);
@@ -224,6 +293,9 @@ int launch_step(pf_ctx *c, const float *frame) {
     void *args[] = {&a};
     HIP_OK(hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(c->block), args, c->lds, c->stream));
     c->cur = 1 - c->cur;
+    if (c->g_cap) ++c->g_len;
+    c->force_anc = nullptr;
+    c->force_nex = nullptr;
     c->step = k;
     c->exchanged = false;
     return PF_OK;
@@ -422,7 +494,7 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map) {
 int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
     if (!c || !o) return PF_EINVAL;
     const uint32_t F = c->cfg.n_filters, M = c->cfg.n_pe;
-    hipLaunchKernelGGL(k_global, dim3(F), dim3(256), 0, c->stream, c->rec[c->cur], c->est, M,
+    hipLaunchKernelGGL(k_global, dim3(F), dim3(256), 0, c->stream, cur_rec(c), c->est, M,
                        c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex, c->cutoff_ppm);
     HIP_OK(hipGetLastError());
     EstDev *e = (EstDev *)malloc(sizeof(EstDev) * F);
@@ -440,7 +512,7 @@ int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
                         c->stream) != hipSuccess ||
          hipMemcpyAsync(&err, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) !=
              hipSuccess ||
-         (want_pe && hipMemcpyAsync(rec, c->rec[c->cur], sizeof(pf_pe_record) * c->FM,
+         (want_pe && hipMemcpyAsync(rec, cur_rec(c), sizeof(pf_pe_record) * c->FM,
                                     hipMemcpyDeviceToHost, c->stream) != hipSuccess) ||
          hipStreamSynchronize(c->stream) != hipSuccess))
         rc = PF_EHIP;
@@ -474,6 +546,151 @@ void pf_destroy(pf_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
+}
+
+int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
+    if (!c || max_steps == 0) return PF_EINVAL;
+    if (c->cfg.lik_mode != PF_LIK_PATCH) return PF_EUNSUPPORTED;
+    if (!(c->cfg.q > 0.f)) return PF_EINVAL;
+    if (c->g_cap || c->exchanged) return PF_ESTATE;
+    const uint64_t N = c->N, FM = c->FM;
+    if (max_steps > 0xFFFFFFFFull - c->step) return PF_EUNSUPPORTED;
+    int rc = PF_OK;
+    if (c->g_alloc < max_steps) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        void *old[] = {c->g_prop, c->g_anc, c->g_rec, c->g_nex};
+        for (void *q : old)
+            if (q) (void)hipFree(q);
+        c->g_prop = nullptr;
+        c->g_anc = nullptr;
+        c->g_rec = nullptr;
+        c->g_nex = nullptr;
+        c->g_alloc = 0;
+        const size_t slots = (size_t)max_steps + 1;
+        rc = dev_alloc(&c->g_prop, slots * 5 * N);
+        if (rc == PF_OK) rc = dev_alloc(&c->g_anc, slots * N);
+        if (rc == PF_OK) rc = dev_alloc(&c->g_rec, slots * FM);
+        if (rc == PF_OK) rc = dev_alloc(&c->g_nex, slots * c->cfg.n_filters);
+        if (rc != PF_OK) return rc;
+        c->g_alloc = max_steps;
+    }
+    for (int i = 0; i < 2 && rc == PF_OK; ++i) {
+        if (!c->g_bar[i]) rc = dev_alloc(&c->g_bar[i], 5 * N);
+        if (rc == PF_OK && !c->g_lbar[i]) rc = dev_alloc(&c->g_lbar[i], 2 * FM);
+    }
+    if (rc == PF_OK && !c->g_theta) rc = dev_alloc(&c->g_theta, 2 * FM);
+    if (rc == PF_OK && !c->g_out) rc = dev_alloc(&c->g_out, 4 * (size_t)c->cfg.n_filters);
+    if (rc != PF_OK) return rc;
+    HIP_OK(hipMemcpyAsync(c->g_prop, c->prop[c->cur], 5 * N * sizeof(float),
+                          hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->g_anc, c->anc[c->cur], N * sizeof(uint16_t), hipMemcpyDeviceToDevice,
+                          c->stream));
+    HIP_OK(hipMemcpyAsync(c->g_rec, c->rec[c->cur], FM * sizeof(pf_pe_record),
+                          hipMemcpyDeviceToDevice, c->stream));
+    c->g_cap = max_steps;
+    c->g_len = 0;
+    c->g_start = c->step;
+    return PF_OK;
+}
+
+int pf_grad_value(pf_ctx *c, double *host_J) {
+    if (!c || !host_J) return PF_EINVAL;
+    if (!c->g_cap) return PF_ESTATE;
+    const uint32_t F = c->cfg.n_filters;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, c->g_len,
+                       (const double *)nullptr, (const float *)nullptr, c->cfg.n_pe,
+                       c->cfg.n_per_pe, (uint32_t)c->N, (uint32_t)c->FM, c->g_out);
+    HIP_OK(hipGetLastError());
+    double *tmp = (double *)malloc(sizeof(double) * 4 * F);
+    if (!tmp) return PF_ENOMEM;
+    int rc = PF_OK;
+    if (hipMemcpyAsync(tmp, c->g_out, 4 * F * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = PF_EHIP;
+    if (rc == PF_OK)
+        for (uint32_t f = 0; f < F; ++f) host_J[f] = tmp[4 * f];
+    free(tmp);
+    return rc;
+}
+
+int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double *host_out) {
+    if (!c || !host_out) return PF_EINVAL;
+    if (!c->g_cap) return PF_ESTATE;
+    const uint32_t F = c->cfg.n_filters, K = c->g_len;
+    if (K && !d_frames) return PF_EINVAL;
+    const uint64_t N = c->N, FM = c->FM;
+    int rc = PF_OK;
+    if (K == 0) {
+        for (uint32_t i = 0; i < 4 * F; ++i) host_out[i] = 0.0;
+    } else {
+        void *fn = pick_adjoint_kernel(c->ppt, c->half);
+        if (!fn) return PF_EUNSUPPORTED;
+        HIP_OK(hipMemsetAsync(c->g_theta, 0, 2 * FM * sizeof(double), c->stream));
+        for (uint32_t i = K; i >= 1 && rc == PF_OK; --i) {
+            const uint64_t k = c->g_start + i;
+            rc = ensure_ring(c, k, true);
+            if (rc != PF_OK) break;
+            StepArgs a;
+            memset(&a, 0, sizeof(a));
+            a.rin = c->g_rec + (size_t)(i - 1) * FM;
+            a.rout = c->g_rec + (size_t)i * FM;
+            a.ring = (c->cfg.mode == PF_MODE_ARNA && c->cfg.n_pe > 1)
+                         ? c->ring_tab + (size_t)(k - c->ring_base) * FM
+                         : nullptr;
+            a.lik = c->lik;
+            a.lik.img = d_frames + (size_t)(i - 1) * frame_stride;
+            a.dyn = c->dyn;
+            a.N = (uint32_t)N;
+            a.M = c->cfg.n_pe;
+            a.np = c->cfg.n_per_pe;
+            a.k = (uint32_t)k;
+            a.key0 = c->key0;
+            a.key1 = c->key1;
+            a.mode = c->cfg.mode;
+            a.first = (k == 1) ? 1u : 0u;
+            a.fixed_nex = c->fixed_nex;
+            a.initial_nex = c->initial_nex;
+            a.cutoff_ppm = c->cutoff_ppm;
+            a.qmax = c->qmax;
+            a.force_nex = c->g_nex + (size_t)i * F;   // N_ex as the forward iteration used it
+            AdjArgs g;
+            g.xprop = c->g_prop + (size_t)i * 5 * N;
+            g.anck = c->g_anc + (size_t)i * N;
+            g.rbar_in = (i == K) ? nullptr : c->g_bar[i & 1];
+            g.rbar_out = c->g_bar[(i - 1) & 1];
+            g.lbar_in = (i == K) ? nullptr : c->g_lbar[i & 1];
+            g.lbar_out = c->g_lbar[(i - 1) & 1];
+            g.theta = c->g_theta;
+            g.sigma = c->cfg.psf_sigma;
+            g.inv_2q = 0.5f / c->cfg.q;
+            void *args[] = {&a, &g};
+            if (hipLaunchKernel(fn, dim3((uint32_t)FM), dim3(c->block), args, 0, c->stream) !=
+                hipSuccess)
+                rc = PF_EHIP;
+        }
+        if (rc == PF_OK) {
+            hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, K,
+                               c->g_theta, c->g_bar[0], c->cfg.n_pe, c->cfg.n_per_pe,
+                               (uint32_t)N, (uint32_t)FM, c->g_out);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(host_out, c->g_out, 4 * F * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream) != hipSuccess)
+                rc = PF_EHIP;
+        }
+    }
+    // the context continues from the last recorded iteration
+    if (hipMemcpyAsync(c->prop[c->cur], c->g_prop + (size_t)K * 5 * N, 5 * N * sizeof(float),
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->anc[c->cur], c->g_anc + (size_t)K * N, N * sizeof(uint16_t),
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->rec[c->cur], c->g_rec + (size_t)K * FM, FM * sizeof(pf_pe_record),
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = PF_EHIP;
+    c->g_cap = 0;
+    c->g_len = 0;
+    return rc;
 }
 
 size_t pf_debug_size(const pf_ctx *c, int which) {
@@ -511,7 +728,7 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
             int rc = dev_alloc(&tmp, 5 * c->N);
             if (rc != PF_OK) return rc;
             hipLaunchKernelGGL(k_materialize, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0,
-                               c->stream, c->prop[c->cur], c->anc[c->cur], tmp, (uint32_t)c->N,
+                               c->stream, cur_prop(c), cur_anc(c), tmp, (uint32_t)c->N,
                                c->cfg.n_per_pe);
             if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
                 hipMemcpy(dst, tmp, need, hipMemcpyDeviceToHost) != hipSuccess)
@@ -519,7 +736,7 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
             (void)hipFree(tmp);
             return rc;
         }
-        case PF_DBG_PE_RECORDS: src = c->rec[c->cur]; break;
+        case PF_DBG_PE_RECORDS: src = cur_rec(c); break;
         case PF_DBG_NEX: src = c->nex_used; break;
         case PF_DBG_RING: src = c->t_pred; break;
         case PF_DBG_V: src = c->t_v; break;
@@ -533,7 +750,7 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
         case PF_DBG_LOGMASS: {
             pf_pe_record *rec = (pf_pe_record *)malloc(sizeof(pf_pe_record) * c->FM);
             if (!rec) return PF_ENOMEM;
-            if (hipMemcpy(rec, c->rec[c->cur], sizeof(pf_pe_record) * c->FM,
+            if (hipMemcpy(rec, cur_rec(c), sizeof(pf_pe_record) * c->FM,
                           hipMemcpyDeviceToHost) != hipSuccess) {
                 free(rec);
                 return PF_EHIP;
@@ -550,6 +767,7 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
 
 int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, uint64_t step) {
     if (!c || !state) return PF_EINVAL;
+    if (c->g_cap) return PF_ESTATE;
     HIP_OK(hipStreamSynchronize(c->stream));
     HIP_OK(hipMemcpy(c->prop[c->cur], state, 5 * c->N * sizeof(float), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_identity, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream,
@@ -565,6 +783,13 @@ int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, ui
     HIP_OK(e);
     c->step = step;
     c->exchanged = false;
+    return PF_OK;
+}
+
+int pf_debug_force_next(pf_ctx *c, const uint32_t *d_anc, const uint32_t *d_nex) {
+    if (!c) return PF_EINVAL;
+    c->force_anc = d_anc;
+    c->force_nex = d_nex;
     return PF_OK;
 }
 

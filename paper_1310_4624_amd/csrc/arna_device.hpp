@@ -249,6 +249,71 @@ __device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
     return patch_loglik<HALF, kFromImageBorder>(s, u0, v0, L.img, 0, L);
 }
 
+// Patch log-likelihood and its partial derivatives for the adjoint step:
+// g = (dl/dx, dl/dy, dl/dI, dl/dsigma) at the frozen patch origin of s (the
+// origin is a step function of the position, held fixed).  With the profiles
+// gx, gy of the forward step, hx = gx d, kx = gx d^2 (d = u0 + j - x) and the
+// row sums R0 = sum gx z, R1 = sum hx z, R2 = sum kx z over a patch row,
+//   A = sum gy R0,  l = (I A - I^2 Sx Sy / 2) / s_n^2,  Sx = sum gx^2,
+//   dA/dx = sum gy R1 / s^2,  dA/dy = sum hy R0 / s^2,
+//   dA/ds = sum (gy R2 + ky R0) / s^3,
+//   dSx/dx = 2 sum gx hx / s^2,  dSx/ds = 2 sum gx kx / s^3  (and in y).
+// Pixels outside the image carry no weight.  The frame is read directly.
+template <int HALF>
+__device__ __forceinline__ float patch_loglik_grad(const float s[5], const Lik &L, float sigma,
+                                                   float g[4]) {
+    constexpr int P = 2 * HALF + 1;
+    g[0] = g[1] = g[2] = g[3] = 0.f;
+    int u0, v0;
+    if (!patch_origin<HALF>(s[0], s[1], L.W, L.H, u0, v0)) return 0.f;
+    float gx[P], gy[P], hx[P], hy[P], kx[P], ky[P];
+    profile<HALF>((float)(u0 + HALF) - s[0], L.inv2s2, L.k2, gx);
+    profile<HALF>((float)(v0 + HALF) - s[1], L.inv2s2, L.k2, gy);
+    float sx = 0.f, sy = 0.f, sxh = 0.f, syh = 0.f, sxk = 0.f, syk = 0.f;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if ((unsigned)(u0 + j) >= (unsigned)L.W) gx[j] = 0.f;
+        if ((unsigned)(v0 + j) >= (unsigned)L.H) gy[j] = 0.f;
+        const float dx = (float)(u0 + j) - s[0], dy = (float)(v0 + j) - s[1];
+        hx[j] = gx[j] * dx;
+        kx[j] = hx[j] * dx;
+        hy[j] = gy[j] * dy;
+        ky[j] = hy[j] * dy;
+        sx += gx[j] * gx[j];
+        sy += gy[j] * gy[j];
+        sxh += gx[j] * hx[j];
+        syh += gy[j] * hy[j];
+        sxk += gx[j] * kx[j];
+        syk += gy[j] * ky[j];
+    }
+    float A = 0.f, Ax = 0.f, Ay = 0.f, As = 0.f;
+#pragma unroll 1
+    for (int jv = 0; jv < P; ++jv) {
+        const int v = min(max(v0 + jv, 0), L.H - 1);
+        const float *row = L.img + (size_t)v * L.W;
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+        for (int ju = 0; ju < P; ++ju) {
+            const int u = min(max(u0 + ju, 0), L.W - 1);
+            const float z = row[u] - L.bg;   // weight 0 where the pixel is outside
+            r0 += gx[ju] * z;
+            r1 += hx[ju] * z;
+            r2 += kx[ju] * z;
+        }
+        A += gy[jv] * r0;
+        Ax += gy[jv] * r1;
+        Ay += hy[jv] * r0;
+        As += gy[jv] * r2 + ky[jv] * r0;
+    }
+    const float I = s[4], k = L.inv_sn2;
+    const float is2 = 2.f * L.inv2s2;   // 1 / s^2
+    g[0] = k * is2 * (I * Ax - I * I * sxh * sy);
+    g[1] = k * is2 * (I * Ay - I * I * syh * sx);
+    g[2] = k * (A - I * sx * sy);
+    g[3] = k * is2 / sigma * (I * As - I * I * (sxk * sy + syk * sx));
+    return (I * A - 0.5f * I * I * (sx * sy)) * k;
+}
+
 // (U), point mode: Gaussian position observation of filter f.
 __device__ __forceinline__ float loglik_point(const float s[5], const Lik &L, uint32_t f) {
     const float dx = s[0] - L.img[2 * f];

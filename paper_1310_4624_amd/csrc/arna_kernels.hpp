@@ -59,6 +59,9 @@ struct StepArgs {
     uint32_t lin_in;                    // which lineage buffer holds iteration k-1
     uint32_t *err;                      // sticky numeric-error flag
     uint32_t *nex_used;                 // [F]
+    uint32_t *nex_rec;                  // [F] N_ex of this iteration, kept for the adjoint; or NULL
+    const uint32_t *force_nex;          // [F] N_ex to use instead of step 2's, or NULL
+    const uint32_t *force_anc;          // [N] ancestors to use instead of step 7's, or NULL
 };
 
 // What a PE knows after steps 1-2 (and the inputs of steps 3-4).
@@ -98,6 +101,7 @@ __device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologu
         p.pred = (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
         p.nex = exchange_count(S, D, M, a.np, a.mode, (int)a.first, a.fixed_nex, a.initial_nex,
                                a.cutoff_ppm);
+        if (a.force_nex) p.nex = a.force_nex[f];
         if (p.nex > a.np) p.nex = a.np;
         const double lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
         if (lglob == -INFINITY) {
@@ -501,6 +505,13 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     // indices are stored (the propagated particles went out in phase 1).
     uint32_t anc[PPT];
     ancestors_from_marks<PPT>(mark, np, L.wq, anc);
+    if (a.force_anc) {   // replay of another run's choices (test support)
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t j = tid * PPT + q;
+            if (j < np) anc[q] = a.force_anc[pe_base + j];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const uint32_t j = tid * PPT + q;
@@ -521,7 +532,10 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         r.lstar = lstar;
         r.total_q = T;
         a.rout[blockIdx.x] = r;
-        if (m == 0) a.nex_used[f] = p.nex;
+        if (m == 0) {
+            a.nex_used[f] = p.nex;
+            if (a.nex_rec) a.nex_rec[f] = p.nex;
+        }
         if (trace) {
             D->t_pred[blockIdx.x] = p.pred;
             D->t_v[blockIdx.x] = V;

@@ -113,6 +113,35 @@ class Tracker:
             p = ctypes.c_void_p(src_map.data_ptr())
         nat.check(nat.lib().pf_exchange(self._h, p), "pf_exchange")
 
+    def grad_begin(self, max_steps: int) -> None:
+        """Record the next max_steps iterations for grad_end."""
+        nat.check(nat.lib().pf_grad_begin(self._h, int(max_steps)), "pf_grad_begin")
+
+    def grad_end(self, frames) -> dict:
+        """Reverse sweep over the recorded iterations (frames: the same frames,
+        first axis = iteration).  Returns J [F] (estimate of the log marginal
+        likelihood of the recorded frames) and grad [F][3], the derivatives
+        of J in (psf_sigma, I0, q) with the discrete choices held fixed."""
+        F = self.F
+        out = np.zeros((F, 4))
+        ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if frames is None or frames.shape[0] == 0:
+            nat.check(nat.lib().pf_grad_end(self._h, None, 0, ptr), "pf_grad_end")
+        else:
+            stride = int(np.prod(frames.shape[1:]))
+            if stride != self.frame_numel():
+                raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
+            nat.check(nat.lib().pf_grad_end(self._h, _dev_ptr(frames, "frames"), stride, ptr),
+                      "pf_grad_end")
+        return dict(J=out[:, 0].copy(), grad=out[:, 1:].copy())
+
+    def grad_value(self) -> np.ndarray:
+        """While recording: J [F] over the iterations recorded so far."""
+        out = np.zeros(self.F)
+        nat.check(nat.lib().pf_grad_value(self._h, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))), "pf_grad_value")
+        return out
+
     def estimate(self, raise_numeric: bool = True) -> dict:
         F, M = self.F, self.M
         out = dict(x_global=np.zeros((F, 5)), x_pe=np.zeros((F, M, 5)),
@@ -164,6 +193,24 @@ class Tracker:
     def set_lineage(self, tags) -> None:
         t = np.ascontiguousarray(np.asarray(tags, dtype=np.int32).reshape(self.N))
         nat.check(nat.lib().pf_debug_set_lineage(self._h, _ptr(t)), "pf_debug_set_lineage")
+
+    def force_next(self, anc=None, nex=None) -> None:
+        """Make the next iteration use these ancestors ([N], slot within the
+        PE, sorted within each PE) and/or N_ex ([F]) instead of its own
+        (replay of another run's choices; test support)."""
+        import torch
+        keep = []
+        ptrs = []
+        for arr, n in ((anc, self.N), (nex, self.F)):
+            if arr is None:
+                ptrs.append(None)
+                continue
+            a = np.ascontiguousarray(np.asarray(arr, dtype=np.uint32).reshape(n))
+            t = torch.from_numpy(a.view(np.int32)).cuda()
+            keep.append(t)
+            ptrs.append(ctypes.c_void_p(t.data_ptr()))
+        self._forced = keep      # alive until the next iteration has run
+        nat.check(nat.lib().pf_debug_force_next(self._h, ptrs[0], ptrs[1]), "pf_debug_force_next")
 
     def close(self) -> None:
         h = getattr(self, "_h", None)
