@@ -105,6 +105,51 @@ def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int):
                 pe_eff=est["pe_eff"].tolist(), n_ex=est["n_ex"].tolist())
 
 
+def grad_leg(workload: str, frames_n: int, seed: int):
+    """Cost of the gradient: K iterations forward, then the same K iterations
+    recorded plus the reverse sweep (pf_grad_end), on the same frames and
+    start.  Both regions are bracketed by events on the library's stream."""
+    import torch
+    from paper_1310_4624_amd import Tracker, synth
+
+    cfg = synth.filter_config(workload, seed=seed)
+    seq = synth.make_sequence(workload, seed=1000, frames=frames_n)
+    frames = torch.from_numpy(seq.frames).cuda()
+    stream = torch.cuda.current_stream()
+    truth = seq.initial_truth()[:cfg["n_filters"]]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # warm-up of both paths (kernel loading, tape allocation)
+    tr = Tracker(cfg, truth)
+    tr.grad_begin(frames_n)
+    tr.run(frames[:2])
+    tr.grad_end(frames[:2])
+    tr.close()
+    torch.cuda.synchronize()
+
+    tr = Tracker(cfg, truth)
+    ev[0].record(stream)
+    tr.run(frames)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    tr.close()
+    tr = Tracker(cfg, truth)
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    tr.grad_begin(frames_n)
+    tr.run(frames)
+    res = tr.grad_end(frames)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    tr.close()
+    fwd = ev[0].elapsed_time(ev[1])
+    both = ev[2].elapsed_time(ev[3])
+    return {"workload": workload, "frames": frames_n,
+            "n_particles": cfg["n_filters"] * cfg["n_pe"] * cfg["n_per_pe"],
+            "fwd_ms": fwd, "fwd_bwd_ms": both, "fwd_bwd_over_fwd": both / fwd,
+            "J": res["J"].tolist(), "dJ_dtheta": res["grad"].tolist(),
+            "theta": ["psf_sigma", "I0", "q"]}
+
+
 def cpu_leg(workload: str, seed: int, budget_s: float, seq):
     """The FP64 oracle on the host cores: whole iterations of the same
     workload on the same frames until the time budget is used (at least one)."""
@@ -140,6 +185,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grad-workload", default="arna_grad_512_256x4096",
+                    choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--grad-frames", type=int, default=50,
+                    help="frames of the fwd+bwd/fwd measurement (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -191,6 +240,10 @@ def main():
         "final_pe_eff": g["pe_eff"],
         "final_n_ex": g["n_ex"],
     }
+    if args.grad_frames:
+        gl = grad_leg(args.grad_workload, args.grad_frames, args.seed)
+        line["fwd_bwd_over_fwd"] = gl["fwd_bwd_over_fwd"]
+        line["grad"] = gl
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_leg(args.workload, args.seed, args.cpu_budget, g["seq"])
     print(json.dumps(line), flush=True)

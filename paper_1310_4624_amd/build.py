@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "arna.hip")
 DEPS = [SRC, os.path.join(PKG, "csrc", "arna_device.hpp"), os.path.join(PKG, "csrc", "arna_kernels.hpp"),
-        os.path.join(ROOT, "include", "arna.h")]
+        os.path.join(PKG, "csrc", "arna_adjoint.hpp"), os.path.join(ROOT, "include", "arna.h")]
 LIB = os.path.join(PKG, "libarna.so")
 ARCH = "gfx950"
 

@@ -92,7 +92,7 @@ struct pf_ctx {
     pf_pe_record *g_rec;           // [g_alloc + 1][F M]
     float *g_bar[2];               // [5][N] adjoints of resampled slots
     double *g_lbar[2];             // [2][F M]
-    double *g_theta;               // [F M][2]
+    double *g_theta;               // [F M][3]
     double *g_out;                 // [F][4]
     uint32_t key0, key1, fixed_nex, initial_nex, cutoff_ppm, qmax;
     Dyn dyn;
@@ -578,7 +578,13 @@ int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
         if (!c->g_bar[i]) rc = dev_alloc(&c->g_bar[i], 5 * N);
         if (rc == PF_OK && !c->g_lbar[i]) rc = dev_alloc(&c->g_lbar[i], 2 * FM);
     }
-    if (rc == PF_OK && !c->g_theta) rc = dev_alloc(&c->g_theta, 2 * FM);
+    if (rc == PF_OK && !c->g_theta) rc = dev_alloc(&c->g_theta, 3 * FM);
+    if (rc == PF_OK) {
+        void *fn = pick_adjoint_kernel(c->ppt, c->half);
+        if (!fn || hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)adjoint_lds_bytes(c->cfg.n_per_pe)) != hipSuccess)
+            rc = PF_EHIP;
+    }
     if (rc == PF_OK && !c->g_out) rc = dev_alloc(&c->g_out, 4 * (size_t)c->cfg.n_filters);
     if (rc != PF_OK) return rc;
     HIP_OK(hipMemcpyAsync(c->g_prop, c->prop[c->cur], 5 * N * sizeof(float),
@@ -598,8 +604,8 @@ int pf_grad_value(pf_ctx *c, double *host_J) {
     if (!c->g_cap) return PF_ESTATE;
     const uint32_t F = c->cfg.n_filters;
     hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, c->g_len,
-                       (const double *)nullptr, (const float *)nullptr, c->cfg.n_pe,
-                       c->cfg.n_per_pe, (uint32_t)c->N, (uint32_t)c->FM, c->g_out);
+                       (const double *)nullptr, c->cfg.n_pe, c->cfg.n_per_pe, (uint32_t)c->FM,
+                       c->g_out);
     HIP_OK(hipGetLastError());
     double *tmp = (double *)malloc(sizeof(double) * 4 * F);
     if (!tmp) return PF_ENOMEM;
@@ -626,7 +632,7 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
     } else {
         void *fn = pick_adjoint_kernel(c->ppt, c->half);
         if (!fn) return PF_EUNSUPPORTED;
-        HIP_OK(hipMemsetAsync(c->g_theta, 0, 2 * FM * sizeof(double), c->stream));
+        HIP_OK(hipMemsetAsync(c->g_theta, 0, 3 * FM * sizeof(double), c->stream));
         for (uint32_t i = K; i >= 1 && rc == PF_OK; --i) {
             const uint64_t k = c->g_start + i;
             rc = ensure_ring(c, k, true);
@@ -665,14 +671,14 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
             g.sigma = c->cfg.psf_sigma;
             g.inv_2q = 0.5f / c->cfg.q;
             void *args[] = {&a, &g};
-            if (hipLaunchKernel(fn, dim3((uint32_t)FM), dim3(c->block), args, 0, c->stream) !=
-                hipSuccess)
+            if (hipLaunchKernel(fn, dim3((uint32_t)FM), dim3(c->block), args,
+                                adjoint_lds_bytes(c->cfg.n_per_pe), c->stream) != hipSuccess)
                 rc = PF_EHIP;
         }
         if (rc == PF_OK) {
             hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, K,
-                               c->g_theta, c->g_bar[0], c->cfg.n_pe, c->cfg.n_per_pe,
-                               (uint32_t)N, (uint32_t)FM, c->g_out);
+                               (const double *)c->g_theta, c->cfg.n_pe, c->cfg.n_per_pe,
+                               (uint32_t)FM, c->g_out);
             if (hipGetLastError() != hipSuccess ||
                 hipMemcpyAsync(host_out, c->g_out, 4 * F * sizeof(double), hipMemcpyDeviceToHost,
                                c->stream) != hipSuccess)

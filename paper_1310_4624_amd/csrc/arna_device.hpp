@@ -250,22 +250,23 @@ __device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
 }
 
 // Patch log-likelihood and its partial derivatives for the adjoint step:
-// g = (dl/dx, dl/dy, dl/dI, dl/dsigma) at the frozen patch origin of s (the
-// origin is a step function of the position, held fixed).  With the profiles
-// gx, gy of the forward step, hx = gx d, kx = gx d^2 (d = u0 + j - x) and the
-// row sums R0 = sum gx z, R1 = sum hx z, R2 = sum kx z over a patch row,
+// g = (dl/dx, dl/dy, dl/dI, dl/dsigma) at the frozen patch origin (u0, v0)
+// (the origin is a step function of the position, held fixed).  With the
+// profiles gx, gy of the forward step, hx = gx d, kx = gx d^2
+// (d = u0 + j - x) and the row sums R0 = sum gx z, R1 = sum hx z,
+// R2 = sum kx z over a patch row,
 //   A = sum gy R0,  l = (I A - I^2 Sx Sy / 2) / s_n^2,  Sx = sum gx^2,
 //   dA/dx = sum gy R1 / s^2,  dA/dy = sum hy R0 / s^2,
 //   dA/ds = sum (gy R2 + ky R0) / s^3,
 //   dSx/dx = 2 sum gx hx / s^2,  dSx/ds = 2 sum gx kx / s^3  (and in y).
-// Pixels outside the image carry no weight.  The frame is read directly.
-template <int HALF>
-__device__ __forceinline__ float patch_loglik_grad(const float s[5], const Lik &L, float sigma,
-                                                   float g[4]) {
+// Pixels outside the image carry no weight.  FROM_TILE: `pix` points at
+// z - B of the patch's first pixel in the LDS tile (row pitch `pitch`, zero
+// outside the image); otherwise the frame is read with clamped indices.
+template <int HALF, bool FROM_TILE>
+__device__ __forceinline__ float patch_loglik_grad(const float s[5], int u0, int v0,
+                                                   const float *pix, int pitch, const Lik &L,
+                                                   float sigma, float g[4]) {
     constexpr int P = 2 * HALF + 1;
-    g[0] = g[1] = g[2] = g[3] = 0.f;
-    int u0, v0;
-    if (!patch_origin<HALF>(s[0], s[1], L.W, L.H, u0, v0)) return 0.f;
     float gx[P], gy[P], hx[P], hy[P], kx[P], ky[P];
     profile<HALF>((float)(u0 + HALF) - s[0], L.inv2s2, L.k2, gx);
     profile<HALF>((float)(v0 + HALF) - s[1], L.inv2s2, L.k2, gy);
@@ -289,16 +290,28 @@ __device__ __forceinline__ float patch_loglik_grad(const float s[5], const Lik &
     float A = 0.f, Ax = 0.f, Ay = 0.f, As = 0.f;
 #pragma unroll 1
     for (int jv = 0; jv < P; ++jv) {
-        const int v = min(max(v0 + jv, 0), L.H - 1);
-        const float *row = L.img + (size_t)v * L.W;
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+        if (FROM_TILE) {
+            typedef __attribute__((address_space(3))) const float lds_f32;
+            lds_f32 *row = (lds_f32 *)pix + jv * pitch;
 #pragma unroll
-        for (int ju = 0; ju < P; ++ju) {
-            const int u = min(max(u0 + ju, 0), L.W - 1);
-            const float z = row[u] - L.bg;   // weight 0 where the pixel is outside
-            r0 += gx[ju] * z;
-            r1 += hx[ju] * z;
-            r2 += kx[ju] * z;
+            for (int ju = 0; ju < P; ++ju) {
+                const float z = row[ju];
+                r0 += gx[ju] * z;
+                r1 += hx[ju] * z;
+                r2 += kx[ju] * z;
+            }
+        } else {
+            const int v = min(max(v0 + jv, 0), L.H - 1);
+            const float *row = L.img + (size_t)v * L.W;
+#pragma unroll
+            for (int ju = 0; ju < P; ++ju) {
+                const int u = min(max(u0 + ju, 0), L.W - 1);
+                const float z = row[u] - L.bg;   // weight 0 where the pixel is outside
+                r0 += gx[ju] * z;
+                r1 += hx[ju] * z;
+                r2 += kx[ju] * z;
+            }
         }
         A += gy[jv] * r0;
         Ax += gy[jv] * r1;

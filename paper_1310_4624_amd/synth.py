@@ -56,6 +56,18 @@ WORKLOADS = {
                  speed=(0.3, 0.6), start_box=(192.0, 320.0), margin=16.0, min_sep=24.0,
                  q_true=0.001),
     ),
+    # Differentiable run: the information-sharing shape (256 PEs x 4096, 512^2,
+    # one spot of SNR 4) over 50 frames, every particle starting at the truth,
+    # so that the intensity gradient is the one of the true initial intensity.
+    "arna_grad_512_256x4096": dict(
+        filter=dict(n_filters=1, n_pe=256, n_per_pe=4096, width=512, height=512, patch=9,
+                    mode=MODE_ARNA, init_mode=INIT_TRACKING, lik_mode=LIK_PATCH,
+                    fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
+                    psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5),
+        seq=dict(width=512, height=512, frames=50, intensities=[8.0], motion="ncv",
+                 speed=(0.3, 0.6), start_box=(192.0, 320.0), margin=16.0, min_sep=24.0,
+                 q_true=0.001),
+    ),
 }
 
 
