@@ -45,7 +45,7 @@ enum {
 
 enum { PF_MODE_RNA = 0, PF_MODE_ARNA = 1 };
 enum { PF_INIT_TRACKING = 0, PF_INIT_INFOSHARE = 1 };
-enum { PF_LIK_PATCH = 0, PF_LIK_POINT = 1 };
+enum { PF_LIK_PATCH = 0, PF_LIK_POINT = 1, PF_LIK_POISSON = 2 };
 
 /* Debug flags (pf_config.debug). */
 enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the last step */
@@ -68,7 +68,10 @@ typedef struct {
     uint32_t mode;              /* PF_MODE_RNA: fixed ring, N_ex = floor(fixed_ratio N_p)
                                    PF_MODE_ARNA: random ring (Sec. IV-B), N_ex by Eq. 3 */
     uint32_t init_mode;         /* PF_INIT_TRACKING or PF_INIT_INFOSHARE (Sec. V) */
-    uint32_t lik_mode;          /* PF_LIK_PATCH (image) or PF_LIK_POINT (position data) */
+    uint32_t lik_mode;          /* PF_LIK_PATCH (image, Gaussian pixel noise),
+                                 * PF_LIK_POINT (position data) or PF_LIK_POISSON
+                                 * (image of photon counts: Poisson pixel noise around
+                                 * B + I g, the noise of the paper's Fig. 1; needs B > 0) */
     float fixed_ratio;          /* RNA exchange ratio N_ex/N_p, in [0, 1] */
     float initial_ratio;        /* ARNA ratio of the first iteration, in [0, 1] */
     float eff_cutoff;           /* ARNA: no exchange when PE_eff > eff_cutoff * M;

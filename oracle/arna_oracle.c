@@ -51,6 +51,7 @@
 #define ORC_INIT_INFOSHARE 1
 #define ORC_LIK_PATCH 0
 #define ORC_LIK_POINT 1
+#define ORC_LIK_POISSON 2
 
 /* Philox stream tags (counter word 3, bits 24..31). */
 #define TAG_INIT 1u
@@ -281,7 +282,10 @@ static particle propagate(particle p, const double eps[5], double q, double sigm
  *   l = sum_patch [ (z - B)^2 - (z - B - I g)^2 ] / (2 sigma_n^2).
  * Pixels outside the image are skipped.  Pixel (u, v) has its centre at
  * x = u (column), y = v (row).
- * Point mode: z is an observed position, l = -|(x, y) - z|^2 / (2 sigma_n^2). */
+ * Point mode: z is an observed position, l = -|(x, y) - z|^2 / (2 sigma_n^2).
+ * Poisson mode: every pixel is a photon count z ~ Poisson(B + I g) (the noise
+ * of the paper's synthetic images, Fig. 1); against the background-only
+ * model, log p(z | B + I g) - log p(z | B) = z log(1 + I g / B) - I g. */
 static double log_likelihood(const orc_config *c, const float *frame, uint32_t f, particle p)
 {
     double s2 = c->noise_sigma * c->noise_sigma;
@@ -302,9 +306,13 @@ static double log_likelihood(const orc_config *c, const float *frame, uint32_t f
             double dx = (double)u - p.x, dy = (double)v - p.y;
             double g = exp(-(dx * dx + dy * dy) / (2.0 * c->psf_sigma * c->psf_sigma));
             double z = (double)frame[(size_t)v * c->width + u];
-            double r0 = z - c->background;
-            double r1 = r0 - p.I * g;
-            l += (r0 * r0 - r1 * r1) / (2.0 * s2);
+            if (c->lik_mode == ORC_LIK_POISSON) {
+                l += z * log1p(p.I * g / c->background) - p.I * g;
+            } else {
+                double r0 = z - c->background;
+                double r1 = r0 - p.I * g;
+                l += (r0 * r0 - r1 * r1) / (2.0 * s2);
+            }
         }
     }
     return l;

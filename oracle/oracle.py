@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_RNA, MODE_ARNA = 0, 1
 INIT_TRACKING, INIT_INFOSHARE = 0, 1
-LIK_PATCH, LIK_POINT = 0, 1
+LIK_PATCH, LIK_POINT, LIK_POISSON = 0, 1, 2
 
 
 def build(force: bool = True) -> str:

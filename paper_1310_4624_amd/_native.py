@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libarna.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENUMERIC, PF_ESTATE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PF_MODE_RNA, PF_MODE_ARNA = 0, 1
 PF_INIT_TRACKING, PF_INIT_INFOSHARE = 0, 1
-PF_LIK_PATCH, PF_LIK_POINT = 0, 1
+PF_LIK_PATCH, PF_LIK_POINT, PF_LIK_POISSON = 0, 1, 2
 PF_DEBUG_TRACE, PF_DEBUG_LINEAGE = 1, 2
 PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 4096, 15
 

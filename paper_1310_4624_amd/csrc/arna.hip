@@ -129,25 +129,25 @@ pf_pe_record *cur_rec(pf_ctx *c) {
     return c->g_cap ? c->g_rec + (size_t)c->g_len * c->FM : c->rec[c->cur];
 }
 
-template <int PPT, int HALF, bool POINT>
+template <int PPT, int HALF, int LIK>
 void *step_kernel() {
-    return reinterpret_cast<void *>(&k_step<PPT, HALF, POINT>);
+    return reinterpret_cast<void *>(&k_step<PPT, HALF, LIK>);
 }
 
-void *pick_step_kernel(uint32_t ppt, uint32_t half, bool point) {
-#define ARNA_HALVES(P)                            \
-    switch (half) {                               \
-        case 0: return step_kernel<P, 0, false>(); \
-        case 1: return step_kernel<P, 1, false>(); \
-        case 2: return step_kernel<P, 2, false>(); \
-        case 3: return step_kernel<P, 3, false>(); \
-        case 4: return step_kernel<P, 4, false>(); \
-        case 5: return step_kernel<P, 5, false>(); \
-        case 6: return step_kernel<P, 6, false>(); \
-        case 7: return step_kernel<P, 7, false>(); \
-        default: return nullptr;                  \
+template <int LIK>
+void *pick_patch_kernel(uint32_t ppt, uint32_t half) {
+#define ARNA_HALVES(P)                          \
+    switch (half) {                             \
+        case 0: return step_kernel<P, 0, LIK>(); \
+        case 1: return step_kernel<P, 1, LIK>(); \
+        case 2: return step_kernel<P, 2, LIK>(); \
+        case 3: return step_kernel<P, 3, LIK>(); \
+        case 4: return step_kernel<P, 4, LIK>(); \
+        case 5: return step_kernel<P, 5, LIK>(); \
+        case 6: return step_kernel<P, 6, LIK>(); \
+        case 7: return step_kernel<P, 7, LIK>(); \
+        default: return nullptr;                \
     }
-    if (point) return ppt == 1 ? step_kernel<1, 0, true>() : step_kernel<4, 0, true>();
     if (ppt == 1) {
         ARNA_HALVES(1)
     } else {
@@ -155,6 +155,13 @@ void *pick_step_kernel(uint32_t ppt, uint32_t half, bool point) {
     }
 #undef ARNA_HALVES
     return nullptr;
+}
+
+void *pick_step_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT)
+        return ppt == 1 ? step_kernel<1, 0, kLikPoint>() : step_kernel<4, 0, kLikPoint>();
+    if (lik_mode == PF_LIK_POISSON) return pick_patch_kernel<kLikPoisson>(ppt, half);
+    return pick_patch_kernel<kLikGauss>(ppt, half);
 }
 
 template <int PPT, int HALF>
@@ -188,8 +195,9 @@ int validate(const pf_config *c) {
     if (!c || c->struct_size != sizeof(pf_config)) return PF_EINVAL;
     if (c->n_filters == 0 || c->n_pe == 0 || c->n_per_pe == 0) return PF_EINVAL;
     if (c->n_pe > PF_MAX_PE || c->n_per_pe > PF_MAX_PER_PE) return PF_EUNSUPPORTED;
-    if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 1) return PF_EINVAL;
-    if (c->lik_mode == PF_LIK_PATCH) {
+    if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
+    if (c->lik_mode == PF_LIK_POISSON && !(c->background > 0.f)) return PF_EINVAL;
+    if (c->lik_mode != PF_LIK_POINT) {
         if (c->patch == 0 || (c->patch & 1u) == 0) return PF_EINVAL;
         if (c->patch > PF_MAX_PATCH) return PF_EUNSUPPORTED;
     }
@@ -288,7 +296,7 @@ int launch_step(pf_ctx *c, const float *frame) {
     int rc = ensure_ring(c, k);
     if (rc != PF_OK) return rc;
     StepArgs a = make_args(c, k, frame);
-    void *fn = pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode == PF_LIK_POINT);
+    void *fn = pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
     if (!fn) return PF_EUNSUPPORTED;
     void *args[] = {&a};
     HIP_OK(hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(c->block), args, c->lds, c->stream));
@@ -334,7 +342,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->N = c->FM * np;
     c->block = block_of(np);
     c->ppt = np > 1024 ? 4 : 1;
-    c->half = cfg->lik_mode == PF_LIK_PATCH ? cfg->patch / 2 : 0;
+    c->half = cfg->lik_mode != PF_LIK_POINT ? cfg->patch / 2 : 0;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
     c->lds = step_lds(np, lineage);
@@ -354,6 +362,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->lik.inv2s2 = 1.0f / (2.0f * cfg->psf_sigma * cfg->psf_sigma);
     c->lik.k2 = expf(-2.0f * c->lik.inv2s2);
     c->lik.bg = cfg->background;
+    c->lik.inv_bg = cfg->background > 0.f ? 1.0f / cfg->background : 0.f;
     c->lik.inv_sn2 = 1.0f / (cfg->noise_sigma * cfg->noise_sigma);
 
     const uint64_t N = c->N;
@@ -398,7 +407,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     float *d_truth = nullptr;
     if (rc == PF_OK) rc = dev_alloc(&d_truth, 5 * (size_t)F);
     if (rc == PF_OK) {
-        void *fn = pick_step_kernel(c->ppt, c->half, cfg->lik_mode == PF_LIK_POINT);
+        void *fn = pick_step_kernel(c->ppt, c->half, cfg->lik_mode);
         if (!fn ||
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds) !=
                 hipSuccess)

@@ -108,6 +108,7 @@ struct Lik {
     float inv2s2;       // c = 1 / (2 psf_sigma^2)
     float k2;           // exp(-2 c), the step of the profile recurrence
     float bg;           // background level
+    float inv_bg;       // 1 / background (Poisson mode)
     float inv_sn2;      // 1 / noise_sigma^2
 };
 
@@ -236,6 +237,50 @@ __device__ __forceinline__ float patch_loglik(const float s[5], int u0, int v0, 
     }
     const float I = s[4];
     return (I * acc - 0.5f * I * I * (sx2 * sy2)) * L.inv_sn2;
+}
+
+// Poisson patch likelihood: pixel counts z ~ Poisson(B + I g), as the
+// log-likelihood ratio against the background-only model,
+//   l = sum_patch [ z log(1 + I g / B) - I g ],
+// pixels outside the image skipped (g = 0 there).  FROM_TILE: `pix` points at
+// z - B in the LDS tile (row pitch `pitch`); otherwise at the frame's first
+// patch pixel (interior patches) or the frame itself (clamped reads).
+template <int HALF, int SRC>
+__device__ __forceinline__ float patch_loglik_poisson(const float s[5], int u0, int v0,
+                                                      const float *pix, int pitch,
+                                                      const Lik &L) {
+    constexpr int P = 2 * HALF + 1;
+    float gx[P], gy[P];
+    profile<HALF>((float)(u0 + HALF) - s[0], L.inv2s2, L.k2, gx);
+    profile<HALF>((float)(v0 + HALF) - s[1], L.inv2s2, L.k2, gy);
+    const float I = s[4];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if ((unsigned)(u0 + j) >= (unsigned)L.W) gx[j] = 0.f;
+        if ((unsigned)(v0 + j) >= (unsigned)L.H) gy[j] = 0.f;
+        gy[j] *= I;
+    }
+    float acc = 0.f;
+#pragma unroll 3
+    for (int jv = 0; jv < P; ++jv) {
+        float r = 0.f;
+#pragma unroll
+        for (int ju = 0; ju < P; ++ju) {
+            float z;
+            if (SRC == kFromTile || SRC == kFromTileInside) {
+                z = pix[jv * pitch + ju] + L.bg;
+            } else if (SRC == kFromImage) {
+                z = pix[(size_t)jv * L.W + ju];
+            } else {
+                const int v = min(max(v0 + jv, 0), L.H - 1), u = min(max(u0 + ju, 0), L.W - 1);
+                z = pix[(size_t)v * L.W + u];
+            }
+            const float t = gy[jv] * gx[ju];
+            r += z * __logf(1.f + t * L.inv_bg) - t;
+        }
+        acc += r;
+    }
+    return acc;
 }
 
 // Patch likelihood straight from the frame (no LDS tile).

@@ -256,10 +256,13 @@ __device__ __forceinline__ void ancestors_from_marks(const uint32_t *mark, uint3
     for (int q = 0; q < PPT; ++q) anc[q] = anc[q] > before ? anc[q] : before;
 }
 
+// Likelihood variants of k_step.
+enum LikKind { kLikGauss = 0, kLikPoint = 1, kLikPoisson = 2 };
+
 // One ARNA / RNA iteration; one workgroup = one PE (f, m).  Thread t owns the
 // slots s = t + q B, q < PPT (B = blockDim.x), so every global access of a
 // slot level is coalesced.
-template <int PPT, int HALF, bool POINT>
+template <int PPT, int HALF, int LIK>
 __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int P = 2 * HALF + 1;
@@ -296,6 +299,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     }
     int tx0 = 0, ty0 = 0;
     bool tile_on = false, tile_inside = false;
+    constexpr bool POINT = LIK == kLikPoint;
     if (!POINT) {
         const double *xh = a.rin[blockIdx.x].xhat;
         const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
@@ -432,14 +436,22 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
             if (tile_on && (unsigned)du <= (unsigned)(kTileCols - P) &&
                 (unsigned)dv <= (unsigned)(kTileRows - P)) {
                 const float *pix = L.tile + dv * kTilePitch + du;
-                ell = tile_inside
-                          ? patch_loglik<HALF, kFromTileInside>(xs, u0, v0, pix, kTilePitch, a.lik)
-                          : patch_loglik<HALF, kFromTile>(xs, u0, v0, pix, kTilePitch, a.lik);
+                if (LIK == kLikPoisson)
+                    ell = patch_loglik_poisson<HALF, kFromTile>(xs, u0, v0, pix, kTilePitch, a.lik);
+                else
+                    ell = tile_inside
+                              ? patch_loglik<HALF, kFromTileInside>(xs, u0, v0, pix, kTilePitch, a.lik)
+                              : patch_loglik<HALF, kFromTile>(xs, u0, v0, pix, kTilePitch, a.lik);
             } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W && v0 + P <= (int)a.lik.H) {
-                ell = patch_loglik<HALF, kFromImage>(xs, u0, v0,
-                                                     a.lik.img + (size_t)v0 * a.lik.W + u0, 0, a.lik);
+                const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
+                ell = (LIK == kLikPoisson)
+                          ? patch_loglik_poisson<HALF, kFromImage>(xs, u0, v0, pix, 0, a.lik)
+                          : patch_loglik<HALF, kFromImage>(xs, u0, v0, pix, 0, a.lik);
             } else {
-                ell = patch_loglik<HALF, kFromImageBorder>(xs, u0, v0, a.lik.img, 0, a.lik);
+                ell = (LIK == kLikPoisson)
+                          ? patch_loglik_poisson<HALF, kFromImageBorder>(xs, u0, v0, a.lik.img, 0,
+                                                                          a.lik)
+                          : patch_loglik<HALF, kFromImageBorder>(xs, u0, v0, a.lik.img, 0, a.lik);
             }
         }
         bad |= (ell != ell);

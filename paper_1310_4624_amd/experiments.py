@@ -1,14 +1,19 @@
-"""The two benchmark modes of Sec. V on the GPU path.
+"""The benchmark modes of Sec. V on the GPU path.
 
 information sharing (Sec. V-B, Fig. 3): PE 0 starts at the object, every other
   PE uniformly over the state space; we count the iterations until every PE's
   estimate x^m is within a radius of the true position, and record the
   fraction of such PEs and PE_eff / M after every iteration.
+  ``curves`` repeats it at the PE counts of Fig. 3 (24, 96, 192, 384).
 tracking (Sec. V-A, Fig. 2): every PE starts at the true state; we record the
-  RMSE of the master estimate against the truth and the exchange counts.
+  RMSE of the master estimate against the truth and the exchange counts
+  (Gaussian or Poisson pixel noise).
+rmse40 (Fig. 2 right): tracking with 40 particles per PE over growing PE counts.
+scaling (Fig. 2 left): a fixed total of 2^20 particles spread over more and
+  more PEs; the GPU time per iteration of ARNA and RNA-0/10/50%.
 
-Run as ``python -m paper_1310_4624_amd.experiments infoshare|tracking [...]``;
-prints one JSON object.
+Run as ``python -m paper_1310_4624_amd.experiments <what> [...]``; prints one
+JSON object per run.
 """
 from __future__ import annotations
 
@@ -57,10 +62,10 @@ def infoshare(mode: str, seq_seed: int = 1000, filter_seed: int = 1, n_pe: int =
 
 
 def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int = 100,
-             seq=None) -> dict:
-    wl = "arna_tracking_512_4x64x4096"
+             seq=None, workload: str = "arna_tracking_512_4x64x4096", **over) -> dict:
+    wl = workload
     mflag, ratio = MODES[mode]
-    cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, seed=filter_seed)
+    cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, seed=filter_seed, **over)
     seq = seq if seq is not None else synth.make_sequence(wl, seed=seq_seed, frames=steps)
     frames = _frames(seq)
     F = cfg["n_filters"]
@@ -73,14 +78,39 @@ def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int =
         n_ex.append(est["n_ex"].tolist())
     tr.close()
     err2 = np.array(err2)
-    return dict(mode=mode, seq_seed=seq_seed, filter_seed=filter_seed, steps=len(err2),
+    return dict(mode=mode, workload=wl, n_pe=cfg["n_pe"], n_per_pe=cfg["n_per_pe"],
+                seq_seed=seq_seed, filter_seed=filter_seed, steps=len(err2),
                 rmse_per_spot=np.sqrt(err2.mean(axis=0)).tolist(),
                 rmse=float(np.sqrt(err2.mean())), mean_n_ex=np.mean(n_ex, axis=0).tolist())
 
 
+def scaling(mode: str, n_pe: int, total: int = 1 << 20, steps: int = 30, warmup: int = 5,
+            seq=None) -> dict:
+    """GPU time per iteration with `total` particles over n_pe PEs (one spot,
+    512^2, every particle starting at the truth)."""
+    import torch
+    wl = "arna_grad_512_256x4096"
+    mflag, ratio = MODES[mode]
+    cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, n_pe=n_pe,
+                              n_per_pe=total // n_pe)
+    seq = seq if seq is not None else synth.make_sequence(wl, seed=1000, frames=warmup + steps)
+    frames = _frames(seq)
+    tr = Tracker(cfg, seq.initial_truth()[:1])
+    tr.run(frames[:warmup])
+    torch.cuda.synchronize()
+    ms = tr.run_timed(frames[warmup:warmup + steps]).astype(np.float64)
+    est = tr.estimate()
+    tr.close()
+    ks = warmup + 1 + np.arange(steps)
+    ring = (ks - 1) % 64 == 0 if mflag == 1 else np.zeros(steps, bool)
+    return dict(mode=mode, n_pe=n_pe, n_per_pe=total // n_pe, total=total,
+                us_per_step=float(ms[~ring].mean() * 1e3), n_ex=int(est["n_ex"][0]))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["infoshare", "tracking"])
+    ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling"])
+    ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
     ap.add_argument("--modes", default="arna,rna10,rna50,rna0")
     ap.add_argument("--seeds", type=int, default=1)
     ap.add_argument("--n-pe", type=int, default=256)
@@ -89,6 +119,36 @@ def main():
     ap.add_argument("--curves", action="store_true", help="include the per-step curves")
     args = ap.parse_args()
     out = []
+    if args.what == "curves":
+        for n_pe in (24, 96, 192, 384):
+            for s in range(args.seeds):
+                for mode in args.modes.split(","):
+                    r = infoshare(mode, seq_seed=1000 + s, filter_seed=1 + s, n_pe=n_pe,
+                                  n_per_pe=args.n_per_pe, steps=args.steps or 40)
+                    r["pe_eff_over_m_at"] = {str(i): r["pe_eff_over_m"][i - 1]
+                                             for i in (1, 2, 5, 10, 20, 40)
+                                             if i <= len(r["pe_eff_over_m"])}
+                    r["fraction_within_at"] = {str(i): r["fraction_within"][i - 1]
+                                               for i in (1, 2, 5, 10, 20, 40)
+                                               if i <= len(r["fraction_within"])}
+                    if not args.curves:
+                        for k in ("fraction_within", "pe_eff_over_m", "n_ex"):
+                            r.pop(k)
+                    print(json.dumps(r), flush=True)
+        return
+    if args.what == "rmse40":
+        for n_pe in (24, 96, 384, 1536, 6144):
+            for s in range(args.seeds):
+                for mode in args.modes.split(","):
+                    r = tracking(mode, seq_seed=1000 + s, filter_seed=1 + s,
+                                 steps=args.steps or 50, n_pe=n_pe, n_per_pe=40)
+                    print(json.dumps(r), flush=True)
+        return
+    if args.what == "scaling":
+        for n_pe in (256, 512, 1024, 2048, 4096, 8192):
+            for mode in args.modes.split(","):
+                print(json.dumps(scaling(mode, n_pe)), flush=True)
+        return
     for s in range(args.seeds):
         for mode in args.modes.split(","):
             if args.what == "infoshare":
@@ -102,7 +162,7 @@ def main():
                                                if i <= len(r["fraction_within"])}}
             else:
                 r = tracking(mode, seq_seed=1000 + s, filter_seed=1 + s,
-                             steps=args.steps or 100)
+                             steps=args.steps or 100, workload=args.workload)
             out.append(r)
             print(json.dumps(r), flush=True)
 

@@ -21,7 +21,13 @@ import numpy as np
 
 MODE_RNA, MODE_ARNA = 0, 1
 INIT_TRACKING, INIT_INFOSHARE = 0, 1
-LIK_PATCH, LIK_POINT = 0, 1
+LIK_PATCH, LIK_POINT, LIK_POISSON = 0, 1, 2
+
+def poisson_intensity(snr: float, background: float) -> float:
+    """Peak intensity I0 with I0 / sqrt(B + I0) = snr (signal over the noise
+    standard deviation at the spot's peak), for Poisson pixel noise."""
+    return float(0.5 * (snr * snr + np.sqrt(snr ** 4 + 4.0 * snr * snr * background)))
+
 
 # Workloads.  Each entry gives the filter configuration (keys shared by the GPU
 # binding and the oracle) and the recipe of its synthetic sequence.
@@ -55,6 +61,30 @@ WORKLOADS = {
         seq=dict(width=512, height=512, frames=200, intensities=[8.0], motion="ncv",
                  speed=(0.3, 0.6), start_box=(192.0, 320.0), margin=16.0, min_sep=24.0,
                  q_true=0.001),
+    ),
+    # Poisson pixel noise (the noise of the paper's synthetic images), CPU-sized:
+    # 1 spot of SNR 3.7 (I0 = 20 over B = 10 counts), 128^2, RNA 4 x 256.
+    "rna_128_4x256_poisson": dict(
+        filter=dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
+                    mode=MODE_RNA, init_mode=INIT_TRACKING, lik_mode=LIK_POISSON,
+                    fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
+                    psf_sigma=1.5, background=10.0, noise_sigma=1.0, q=0.5, sigma_I=0.5),
+        seq=dict(width=128, height=128, frames=20, intensities=[20.0], motion="constant",
+                 speed=(1.0, 1.0), start_box=(40.0, 88.0), margin=16.0, min_sep=24.0,
+                 noise="poisson"),
+    ),
+    # ARNA tracking with Poisson pixel noise: the tracking workload's shape,
+    # 4 spots of Poisson SNR 2..6 over B = 10 counts.
+    "arna_tracking_512_4x64x4096_poisson": dict(
+        filter=dict(n_filters=4, n_pe=64, n_per_pe=4096, width=512, height=512, patch=9,
+                    mode=MODE_ARNA, init_mode=INIT_TRACKING, lik_mode=LIK_POISSON,
+                    fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
+                    psf_sigma=1.5, background=10.0, noise_sigma=1.0, q=0.5, sigma_I=0.5),
+        seq=dict(width=512, height=512, frames=100,
+                 intensities=[poisson_intensity(s, 10.0) for s in np.linspace(2.0, 6.0, 4)],
+                 motion="ncv",
+                 speed=(0.5, 1.0), start_box=(160.0, 352.0), margin=16.0, min_sep=24.0,
+                 q_true=0.001, noise="poisson"),
     ),
     # Differentiable run: the information-sharing shape (256 PEs x 4096, 512^2,
     # one spot of SNR 4) over 50 frames, every particle starting at the truth,
@@ -141,6 +171,16 @@ def render(truth_k, width, height, psf_sigma, background, noise_sigma, rng):
     return img.astype(np.float32)
 
 
+def render_poisson(truth_k, width, height, psf_sigma, background, rng):
+    """One frame of photon counts: Poisson(B + sum_spots I0 exp(-d^2/(2 s^2)))."""
+    ys, xs = np.mgrid[0:height, 0:width].astype(np.float64)
+    lam = np.full((height, width), float(background))
+    for s in range(truth_k.shape[0]):
+        x, y, _, _, I0 = truth_k[s]
+        lam += I0 * np.exp(-((xs - x) ** 2 + (ys - y) ** 2) / (2 * psf_sigma ** 2))
+    return rng.poisson(lam).astype(np.float32)
+
+
 def make_sequence(workload: str, seed: int = 1000, frames: int | None = None) -> Sequence:
     """Frames and truth for a named workload (sequence seeds 1000.. by convention)."""
     w = WORKLOADS[workload]
@@ -152,8 +192,12 @@ def make_sequence(workload: str, seed: int = 1000, frames: int | None = None) ->
                          sq["margin"], sq["min_sep"], q=sq.get("q_true", fl["q"]))
     out = np.zeros((K, sq["height"], sq["width"]), np.float32)
     for k in range(1, K + 1):
-        out[k - 1] = render(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
-                            fl["background"], fl["noise_sigma"], rng)
+        if sq.get("noise") == "poisson":
+            out[k - 1] = render_poisson(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
+                                        fl["background"], rng)
+        else:
+            out[k - 1] = render(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
+                                fl["background"], fl["noise_sigma"], rng)
     return Sequence(frames=out, truth=truth, spots=len(sq["intensities"]))
 
 

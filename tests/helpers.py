@@ -83,6 +83,44 @@ def ell_tolerance(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, 
     return 1.25 * (Gx * tol_x + Gy * tol_y + GI * tol_I) + 2e-6 * mag + 1e-6
 
 
+def ell_tolerance_poisson(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I):
+    """Per-particle bound on |l_gpu - l_oracle| for Poisson patch mode,
+    l = sum [z log(1 + I g / B) - I g]: the gradient of l times the coordinate
+    tolerances, plus FP32 rounding (the float log of 1 + t/B carries an
+    absolute error of a few 1e-8 per pixel, times the count z)."""
+    x, y, I = prop[0], prop[1], prop[4]
+    half = cfg["patch"] // 2
+    H, W = frame.shape
+    s2 = cfg["psf_sigma"] ** 2
+    B = cfg["background"]
+    cx = np.floor(x + 0.5)
+    cy = np.floor(y + 0.5)
+    ok = np.isfinite(cx) & np.isfinite(cy) & (np.abs(cx) < 1e8) & (np.abs(cy) < 1e8)
+    cxi = np.where(ok, cx, -10 ** 6).astype(np.int64)
+    cyi = np.where(ok, cy, -10 ** 6).astype(np.int64)
+    Gx = np.zeros_like(x)
+    Gy = np.zeros_like(x)
+    GI = np.zeros_like(x)
+    mag = np.zeros_like(x)
+    zsum = np.zeros_like(x)
+    for dv in range(-half, half + 1):
+        v = cyi + dv
+        for du in range(-half, half + 1):
+            u = cxi + du
+            inb = (u >= 0) & (u < W) & (v >= 0) & (v < H)
+            z = np.where(inb, frame[np.clip(v, 0, H - 1), np.clip(u, 0, W - 1)], 0.0)
+            ddx, ddy = u - x, v - y
+            g = np.where(inb, np.exp(-(ddx * ddx + ddy * ddy) / (2 * s2)), 0.0)
+            lam = B + I * g
+            dl_dg = np.abs(z * I / lam - I)
+            Gx += dl_dg * g * np.abs(ddx) / s2
+            Gy += dl_dg * g * np.abs(ddy) / s2
+            GI += z * g / lam - g
+            mag += np.abs(z * np.log1p(I * g / B)) + np.abs(I * g)
+            zsum += z
+    return 1.25 * (Gx * tol_x + Gy * tol_y + np.abs(GI) * tol_I) + 4e-6 * mag + 2e-7 * zsum + 1e-6
+
+
 def check_ancestors(Qg, Vg, ancg, Qo, Vo, anco, tolQ):
     """Compare one PE's ancestors.  The GPU ancestors must be valid for the
     GPU's own fixed-point weights; where they differ from the oracle's, the

@@ -127,6 +127,14 @@ def seeded_case(name):
         truth = np.array([[[64.2, 63.9, 0, 0, 8.0]]])
         frame = synth.render(truth[0], 128, 128, 1.5, 5.0, 2.0, rng)
         centre = truth[0, :, :2]
+    elif name == "poisson_arna_1x4x1000":
+        cfg = dict(n_filters=1, n_pe=4, n_per_pe=1000, width=64, height=48, patch=9,
+                   mode=1, init_mode=0, lik_mode=2, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=10.0, noise_sigma=1.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 4)
+        truth = np.array([[[20.4, 30.6, 0, 0, 20.0], [58.2, 3.1, 0, 0, 15.0]]])
+        frame = synth.render_poisson(truth[0], 64, 48, 1.5, 10.0, rng)
+        centre = truth[0, :1, :2]
     elif name == "point_rna_3x5x77":
         cfg = dict(n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, patch=9,
                    mode=0, init_mode=0, lik_mode=1, fixed_ratio=0.5, initial_ratio=0.1,
@@ -162,7 +170,7 @@ def run_one_step(cfg, frame, state, logmass, k_done):
 
 
 @pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
-                                  "point_rna_3x5x77"])
+                                  "poisson_arna_1x4x1000", "point_rna_3x5x77"])
 @pytest.mark.parametrize("k_done", [0, 7])
 def test_one_step_parity(name, k_done):
     cfg, frame, state, logmass = seeded_case(name)
@@ -180,12 +188,12 @@ def test_one_step_parity(name, k_done):
                     H.coord_tol(tr["prop"][4])])
     assert np.all(np.abs(g["prop"] - tr["prop"]) <= tol)
     # log-likelihoods, except particles on a pixel boundary
-    if cfg["lik_mode"] == 0:
+    if cfg["lik_mode"] in (0, 2):
         tl = np.zeros(N)
+        bound = H.ell_tolerance if cfg["lik_mode"] == 0 else H.ell_tolerance_poisson
         for f in range(F):
             sl = slice(f * M * n_p, (f + 1) * M * n_p)
-            tl[sl] = H.ell_tolerance(cfg, frame, tr["prop"][:, sl], tol[0][sl], tol[1][sl],
-                                     tol[4][sl])
+            tl[sl] = bound(cfg, frame, tr["prop"][:, sl], tol[0][sl], tol[1][sl], tol[4][sl])
         flip = H.patch_flip_mask(tr["prop"][0], tr["prop"][1], tol[0], tol[1])
     else:
         d = np.hypot(tr["prop"][0] - np.repeat(frame[:, 0], M * n_p),
