@@ -72,6 +72,9 @@ struct pf_ctx {
     uint64_t ring_base;
     bool ring_valid;
     uint32_t *err, *nex_used;
+    // master records (used when M >= kMasterMinPE), ping-pong like the records
+    MasterRec *mrec[2];
+    uint32_t *arrive;
     EstDev *est;
     DebugBufs *d_dbg;              // device copy of the debug-buffer table, or NULL
     // trace buffers
@@ -100,6 +103,10 @@ struct pf_ctx {
 };
 
 namespace {
+
+// From this many PEs per filter on, the master step is computed once per
+// filter (by its last workgroup) instead of by every PE of the next iteration.
+constexpr uint32_t kMasterMinPE = 2048;
 
 #define HIP_OK(expr)                                      \
     do {                                                  \
@@ -222,6 +229,7 @@ void free_all(pf_ctx *c) {
                     c->lin[0], c->lin[1],
                     c->ring_tab, c->err, c->nex_used, c->est, c->t_pred, c->t_q, c->t_anc,
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
+                    c->mrec[0], c->mrec[1], c->arrive,
                     c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
                     c->g_lbar[1], c->g_theta, c->g_out};
     for (void *p : ptrs)
@@ -254,6 +262,11 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     a.rin = cur_rec(c);
     a.force_anc = c->force_anc;
     a.force_nex = c->force_nex;
+    if (c->mrec[0]) {
+        a.min = c->mrec[c->cur];
+        a.mout = c->mrec[nxt];
+        a.arrive = c->arrive;
+    }
     if (c->g_cap) {
         a.nex_rec = c->g_nex + (size_t)(c->g_len + 1) * c->cfg.n_filters;
         a.pout = c->g_prop + (size_t)(c->g_len + 1) * 5 * c->N;
@@ -287,6 +300,17 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     a.err = c->err;
     a.nex_used = c->nex_used;
     return a;
+}
+
+// Master records of the records in buffer `which` (after initialization or a
+// state load), when the context uses them.
+int refresh_master(pf_ctx *c, int which) {
+    if (!c->mrec[0]) return PF_OK;
+    hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(256), 0, c->stream,
+                       c->rec[which], c->mrec[which], c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
+                       c->fixed_nex, c->cutoff_ppm);
+    HIP_OK(hipGetLastError());
+    return PF_OK;
 }
 
 int launch_step(pf_ctx *c, const float *frame) {
@@ -375,6 +399,11 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     }
     if (rc == PF_OK && cfg->mode == PF_MODE_ARNA && M > 1)
         rc = dev_alloc(&c->ring_tab, (size_t)kRingSteps * c->FM);
+    if (rc == PF_OK && M >= kMasterMinPE) {
+        rc = dev_alloc(&c->mrec[0], F);
+        if (rc == PF_OK) rc = dev_alloc(&c->mrec[1], F);
+        if (rc == PF_OK) rc = dev_alloc(&c->arrive, F);
+    }
     if (rc == PF_OK) rc = dev_alloc(&c->err, 1);
     if (rc == PF_OK) rc = dev_alloc(&c->nex_used, F);
     if (rc == PF_OK) rc = dev_alloc(&c->est, F);
@@ -417,7 +446,9 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
         if (hipMemcpyAsync(d_truth, truth, 5 * F * sizeof(float), hipMemcpyHostToDevice,
                            c->stream) != hipSuccess ||
             hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
-            hipMemsetAsync(c->nex_used, 0, F * sizeof(uint32_t), c->stream) != hipSuccess)
+            hipMemsetAsync(c->nex_used, 0, F * sizeof(uint32_t), c->stream) != hipSuccess ||
+            (c->arrive &&
+             hipMemsetAsync(c->arrive, 0, F * sizeof(uint32_t), c->stream) != hipSuccess))
             rc = PF_EHIP;
     }
     if (rc == PF_OK) {
@@ -427,8 +458,9 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
                            cfg->width,
                            cfg->height, cfg->init_mode == PF_INIT_INFOSHARE ? 1u : 0u, c->key0,
                            c->key1, (uint32_t)c->FM);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
-            rc = PF_EHIP;
+        if (hipGetLastError() != hipSuccess) rc = PF_EHIP;
+        if (rc == PF_OK) rc = refresh_master(c, 0);
+        if (rc == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = PF_EHIP;
     }
     if (d_truth) (void)hipFree(d_truth);
     if (rc != PF_OK) {
@@ -796,6 +828,9 @@ int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, ui
         hipMemcpy(c->rec[c->cur], rec, sizeof(pf_pe_record) * c->FM, hipMemcpyHostToDevice);
     free(rec);
     HIP_OK(e);
+    const int rc = refresh_master(c, c->cur);
+    if (rc != PF_OK) return rc;
+    HIP_OK(hipStreamSynchronize(c->stream));
     c->step = step;
     c->exchanged = false;
     return PF_OK;

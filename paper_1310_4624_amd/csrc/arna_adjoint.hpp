@@ -97,7 +97,7 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
     bool tile_on = false;
     {
         const double *xh = a.rout[blockIdx.x].xhat;
-        if (fabs(xh[0]) < 1e6 && fabs(xh[1]) < 1e6) {   // false for NaN (a PE without mass)
+        if (B >= 1024 && fabs(xh[0]) < 1e6 && fabs(xh[1]) < 1e6) {   // false for NaN
             tx0 = (int)floor(xh[0] + 0.5) - kTileCols / 2;
             ty0 = (int)floor(xh[1] + 0.5) - kTileRows / 2;
             tile_on = tx0 < a.lik.W && tx0 + kTileCols > 0 && ty0 < a.lik.H && ty0 + kTileRows > 0;

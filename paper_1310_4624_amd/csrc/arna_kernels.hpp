@@ -28,6 +28,16 @@ struct EstDev {                         // written by k_global, one per filter
     uint32_t pad;
 };
 
+// The master step of an iteration (Alg. 3 steps 9-10 and the input of step 2
+// of the next), per filter: log W = log sum_m W^(m) and the next N_ex.  For
+// many PEs it is computed once, by the last workgroup of the filter to
+// finish, instead of by every PE of the next iteration.
+struct MasterRec {
+    double lglob;
+    uint32_t nex_next;
+    uint32_t pad;
+};
+
 // Buffers kept only in debug modes (one device copy per context).
 struct DebugBufs {
     // trace of the last iteration (PF_DEBUG_TRACE), else NULL
@@ -62,6 +72,12 @@ struct StepArgs {
     uint32_t *nex_rec;                  // [F] N_ex of this iteration, kept for the adjoint; or NULL
     const uint32_t *force_nex;          // [F] N_ex to use instead of step 2's, or NULL
     const uint32_t *force_anc;          // [N] ancestors to use instead of step 7's, or NULL
+    // master steps (many PEs): of k-1, read by the prologue, and of k, written
+    // by the last workgroup of each filter to finish; NULL: every PE
+    // recomputes the master step from the M records
+    const MasterRec *min;
+    MasterRec *mout;
+    uint32_t *arrive;                   // [F] workgroups of the filter done with k
 };
 
 // What a PE knows after steps 1-2 (and the inputs of steps 3-4).
@@ -115,6 +131,74 @@ __device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologu
         p.c_pred = mulshift(philox(p.pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
         *out = p;
     }
+}
+
+// The prologue from a precomputed master record (lane 0 of one wave).
+__device__ void prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out) {
+    if ((threadIdx.x & (kWave - 1)) != 0) return;
+    const uint32_t M = a.M;
+    const pf_pe_record *R = a.rin + (size_t)f * M;
+    const MasterRec mr = a.min[f];
+    Prologue p;
+    p.pred = (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
+    if (M <= 1)
+        p.nex = 0;
+    else if (a.mode == 0)
+        p.nex = a.fixed_nex;
+    else if (a.first)
+        p.nex = a.initial_nex;
+    else
+        p.nex = mr.nex_next;
+    if (a.force_nex) p.nex = a.force_nex[f];
+    if (p.nex > a.np) p.nex = a.np;
+    if (mr.lglob == -INFINITY) {
+        p.lam_own = 0.f;
+        p.lam_pred = 0.f;
+    } else {
+        p.lam_own = (float)(R[m].log_mass - mr.lglob);
+        p.lam_pred = (float)(R[p.pred].log_mass - mr.lglob);
+    }
+    p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
+    p.c_pred = mulshift(philox(p.pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
+    *out = p;
+}
+
+// Master record of filter f from its M PE records, by the whole workgroup
+// (`red` >= 3 doubles per wave); thread 0 writes it.
+__device__ void master_block(const pf_pe_record *R, uint32_t M, uint32_t np, uint32_t mode,
+                             uint32_t fixed_nex, uint32_t cutoff_ppm, double *red,
+                             MasterRec *out) {
+    double lmax = -INFINITY;
+    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) lmax = fmax(lmax, R[i].log_mass);
+    lmax = block_max_d(lmax, red);
+    double acc[1] = {0.0};
+    uint64_t sd[2] = {0, 0};
+    if (lmax != -INFINITY)
+        for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
+            const double e = exp(R[i].log_mass - lmax);
+            const uint64_t P = (uint64_t)floor(e * 1048576.0);
+            acc[0] += e;
+            sd[0] += P;
+            sd[1] += P * P;
+        }
+    block_sum<1>(acc, red);
+    block_sum_u64(sd, (uint64_t *)red);
+    if (threadIdx.x == 0) {
+        MasterRec r;
+        r.lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
+        r.nex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
+        r.pad = 0;
+        *out = r;
+    }
+}
+
+// Master records of every filter (after initialization or a state load).
+__global__ __launch_bounds__(256) void k_master(const pf_pe_record *rec, MasterRec *out,
+                                                uint32_t M, uint32_t np, uint32_t mode,
+                                                uint32_t fixed_nex, uint32_t cutoff_ppm) {
+    __shared__ double red[kRedDoubles];
+    master_block(rec + (size_t)blockIdx.x * M, M, np, mode, fixed_nex, cutoff_ppm, red,
+                 out + blockIdx.x);
 }
 
 // Step 3: PE m sends its slots s_t(m) = floor((t N_p + c_m) / N_ex), t < N_ex,
@@ -286,7 +370,12 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     // tile is centred where this PE's estimate of k-1 moves in one step
     // (x + v); a particle whose patch does not fit in it reads the frame,
     // with the same arithmetic.
-    if (wave == 0) prologue_wave(a, f, m, L.pro);
+    if (wave == 0) {
+        if (a.min)
+            prologue_master(a, f, m, L.pro);
+        else
+            prologue_wave(a, f, m, L.pro);
+    }
     uint32_t own[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -303,7 +392,8 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     if (!POINT) {
         const double *xh = a.rin[blockIdx.x].xhat;
         const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
-        if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
+        // the tile pays for its 4096 loads only with a full workgroup of particles
+        if (B >= 1024 && fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
             tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
             ty0 = (int)floor(cy + 0.5) - kTileRows / 2;
             tile_on = tx0 < (int)a.lik.W && tx0 + kTileCols > 0 && ty0 < (int)a.lik.H &&
@@ -551,6 +641,23 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         if (trace) {
             D->t_pred[blockIdx.x] = p.pred;
             D->t_v[blockIdx.x] = V;
+        }
+    }
+    if (a.mout) {
+        // the last workgroup of the filter to publish its record computes the
+        // master step of this iteration (records made visible by the fence
+        // before the arrival count; the counter is reset for the next one)
+        uint32_t *last = (uint32_t *)L.wmax;
+        if (tid == 0) {
+            __threadfence();
+            *last = (atomicAdd(&a.arrive[f], 1u) == M - 1) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (*last) {
+            __threadfence();
+            master_block(a.rout + (size_t)f * M, M, np, a.mode, a.fixed_nex, a.cutoff_ppm,
+                         L.wsum, a.mout + f);
+            if (tid == 0) atomicExch(&a.arrive[f], 0u);
         }
     }
 }

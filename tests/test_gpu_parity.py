@@ -135,6 +135,15 @@ def seeded_case(name):
         truth = np.array([[[20.4, 30.6, 0, 0, 20.0], [58.2, 3.1, 0, 0, 15.0]]])
         frame = synth.render_poisson(truth[0], 64, 48, 1.5, 10.0, rng)
         centre = truth[0, :1, :2]
+    elif name == "arna_2x2100x4":
+        # many small PEs: the master step is computed once per filter
+        cfg = dict(n_filters=2, n_pe=2100, n_per_pe=4, width=96, height=80, patch=9,
+                   mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 5)
+        truth = np.array([[[30.3, 40.7, 0, 0, 12.0], [70.6, 20.2, 0, 0, 9.0]]])
+        frame = synth.render(truth[0], 96, 80, 1.5, 5.0, 2.0, rng)
+        centre = truth[0, :, :2]
     elif name == "point_rna_3x5x77":
         cfg = dict(n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, patch=9,
                    mode=0, init_mode=0, lik_mode=1, fixed_ratio=0.5, initial_ratio=0.1,
@@ -170,7 +179,7 @@ def run_one_step(cfg, frame, state, logmass, k_done):
 
 
 @pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
-                                  "poisson_arna_1x4x1000", "point_rna_3x5x77"])
+                                  "poisson_arna_1x4x1000", "arna_2x2100x4", "point_rna_3x5x77"])
 @pytest.mark.parametrize("k_done", [0, 7])
 def test_one_step_parity(name, k_done):
     cfg, frame, state, logmass = seeded_case(name)
@@ -219,14 +228,55 @@ def test_one_step_parity(name, k_done):
         mism += H.check_ancestors(g["q"][sl], g["v"][f, m], g["ancestors"][sl], tr["Q"][sl],
                                   tr["V"][f, m], tr["anc"][sl], tq)
     assert mism <= max(2, N // 200)
-    # estimates: per PE and global, 1e-4
+    # estimates: per PE (those without a particle on a pixel boundary, whose
+    # weight may legitimately differ) within 1e-4, or, for PEs of a few
+    # particles, within what the weight tolerances allow: a weight error du_i
+    # moves x^m by sum w_i du_i |x_i - x^m| / sum w_i (both sides, plus the
+    # coordinate tolerance); global within 1e-4
     rec = g["pe_records"]
-    assert np.allclose(rec[:, :, 1:6], tr["xhat_pe"], rtol=0, atol=1e-4)
+    pe_ok = ~flip.reshape(F, M, n_p).any(axis=2)
+    u = (tr["lambda"] + tr["ell"]).reshape(F * M, n_p)
+    w = np.exp(u - u.max(axis=1, keepdims=True))
+    du = (tl + 1e-6 * (1 + np.abs(tr["lambda"]))).reshape(F * M, n_p)
+    xo = tr["prop"].reshape(5, F * M, n_p)
+    xm = tr["xhat_pe"].reshape(F * M, 5).T
+    bound = (2 * (w * du * np.abs(xo - xm[:, :, None])).sum(axis=2) / w.sum(axis=1)
+             + tol.reshape(5, F * M, n_p).max(axis=2)).T.reshape(F, M, 5)
+    err = np.abs(rec[:, :, 1:6] - tr["xhat_pe"])
+    assert np.all(err[pe_ok] <= np.maximum(1e-4, bound[pe_ok])), float(err[pe_ok].max())
     assert np.allclose(g["est"]["x_global"], tr["xhat"], rtol=0, atol=1e-4)
     assert np.allclose(rec[:, :, 0], tr["L_pe"], rtol=1e-5, atol=1e-3)
     assert np.allclose(g["est"]["log_z_inc"], tr["log_z"], rtol=1e-5, atol=1e-3)
     assert np.array_equal(g["est"]["n_ex_next"], tr["n_ex_next"])
     assert np.allclose(g["est"]["pe_eff"], tr["pe_eff"], rtol=1e-4)
+
+
+def test_master_step_of_many_pes():
+    """With many PEs the last workgroup of each filter computes the master
+    step once: the next iteration's N_ex equals the one the master step
+    reports from the same records, and the carried weights are the records'
+    log-masses renormalized by their log-sum-exp, over several iterations."""
+    p = pf()
+    cfg, frame, state, logmass = seeded_case("arna_2x2100x4")
+    F, M = cfg["n_filters"], cfg["n_pe"]
+    g = p.Tracker(cfg, np.zeros((F, 5), np.float32), debug=p.PF_DEBUG_TRACE)
+    g.set_state(state, logmass, step=3)
+    fr = torch.from_numpy(frame).cuda()
+    prev = g.estimate()
+    L_prev = logmass
+    for it in range(4):
+        g.step(fr)
+        est = g.estimate()
+        if it > 0:
+            assert np.array_equal(est["n_ex"], prev["n_ex_next"]), it
+        lam = g.debug_get("lam").reshape(F, M, -1)
+        src = g.debug_get("src").reshape(F, M, -1) // cfg["n_per_pe"] % M
+        for f in range(F):
+            lse = np.logaddexp.reduce(L_prev[f])
+            want = L_prev[f][src[f]] - lse
+            assert np.allclose(lam[f], want, rtol=1e-6, atol=1e-5), (it, f)
+        prev, L_prev = est, est["log_mass_pe"]
+    g.close()
 
 
 def test_exchange_map_export():
