@@ -52,7 +52,7 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, ring_groups: int = 0):
     """HBM bytes per k_step launch from the committed counter summary, or None
     when the kernel sources changed since it was taken."""
     try:
@@ -60,16 +60,17 @@ def measured_traffic(workload: str):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+    if (t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload
+            or t.get("ring_groups", 0) != ring_groups):
         return None
     return t.get("bytes_per_launch")
 
 
-def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int):
+def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int, ring_groups: int = 0):
     import torch
     from paper_1310_4624_amd import Tracker, synth
 
-    cfg = synth.filter_config(workload, seed=seed)
+    cfg = synth.filter_config(workload, seed=seed, ring_groups=ring_groups)
     n_frames = max(warmup + steps + probe, synth.WORKLOADS[workload]["seq"]["frames"])
     seq = synth.make_sequence(workload, seed=1000, frames=n_frames)
     F = cfg["n_filters"]
@@ -183,6 +184,8 @@ def main():
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096",
                     choices=sorted(synth.WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--ring-groups", type=int, default=0,
+                    help="ARNA hardware-aware ring with this many PE groups (8: one per die)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad-workload", default="arna_grad_512_256x4096",
@@ -207,7 +210,7 @@ def main():
               "multi-GPU sharding of the path is a design note, not code", file=sys.stderr)
         sys.exit(2)
 
-    g = gpu_leg(args.workload, args.steps, args.warmup, args.seed, args.probe)
+    g = gpu_leg(args.workload, args.steps, args.warmup, args.seed, args.probe, args.ring_groups)
     cfg = g["cfg"]
     N = cfg["n_filters"] * cfg["n_pe"] * cfg["n_per_pe"]
     ms = g["total_ms"] / args.steps
@@ -233,10 +236,11 @@ def main():
                    "n_pe": cfg["n_pe"], "n_per_pe": cfg["n_per_pe"],
                    "frame": f"{cfg['width']}x{cfg['height']}", "patch": cfg["patch"],
                    "mode": "ARNA" if cfg["mode"] == 1 else "RNA",
+                   "ring_groups": cfg.get("ring_groups", 0),
                    "parallelism": "one PE per workgroup, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload),
+                     "traffic": measured_traffic(args.workload, args.ring_groups),
                      "kernel": "k_step", "kernel_ms": ms,
                      "event_ms_per_launch": g["step_kernel_ms"],
                      "bytes_per_launch": bytes_launch, "kernel_sha": kernel_sha()},

@@ -82,6 +82,13 @@ typedef struct {
     float q;                    /* NCV process-noise intensity (px^2), >= 0 */
     float sigma_I;              /* intensity random-walk std, >= 0 */
     uint32_t debug;             /* PF_DEBUG_* flags */
+    uint32_t ring_groups;       /* ARNA ring: 0 or 1 = one random ring over all PEs
+                                 * (Sec. IV-B); G in 2..256 = hardware-aware ring (the
+                                 * future work of Sec. VI): PE m of filter f is in group
+                                 * (f M + m) mod G -- with G = 8 the MI355X die its
+                                 * workgroup runs on -- and the ring visits the groups in
+                                 * a random order and each group's PEs in a random order,
+                                 * so only G of its M edges join different groups */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;
@@ -231,7 +238,7 @@ int pf_debug_nex(const uint32_t *p, uint32_t M, uint32_t n_p, uint32_t mode, flo
                  float initial_ratio, float eff_cutoff, int first_iteration, uint32_t *nex_out);
 /* Ring of iteration k of filter f (Alg. 3, step 1): pred_out[M]. */
 int pf_debug_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t mode,
-                  uint32_t *pred_out);
+                  uint32_t groups, uint32_t *host_pred_out);
 /* Philox4x32-10 of n counters: ctr [n][4], key [2], out [n][4]. */
 int pf_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t n, uint32_t *out);
 

@@ -132,6 +132,53 @@ void orc_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, int mode,
     free(p);
 }
 
+/* Hardware-aware variant of step 1 (the future work of Sec. VI): the PEs are
+ * split into G groups, PE m of filter f in group (f M + m) mod G (on MI355X,
+ * with G = 8, the accelerator die its workgroup runs on); the members of each
+ * group, in increasing m, are shuffled by Durstenfeld with the draws
+ * Philox(i, k, f, RING | 2 + g), the order of the groups by Durstenfeld with
+ * Philox(i, k, f, RING | 1); the ring visits the groups in that order, each
+ * group's members in their shuffled order, and closes.  Only G of its M edges
+ * join different groups.  G <= 1 is the ring of orc_ring. */
+void orc_ring_groups(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t G,
+                     uint32_t *pi, uint32_t *pred, uint32_t *succ)
+{
+    if (G <= 1 || M <= 1) {
+        orc_ring(seed, f, k, M, ORC_MODE_ARNA, pi, pred, succ);
+        return;
+    }
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * G);
+    uint32_t *members = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    uint32_t *p = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    for (uint32_t g = 0; g < G; ++g) order[g] = g;
+    for (uint32_t i = G - 1; i >= 1; --i) {
+        uint32_t r[4];
+        draw(seed, TAG_RING, 1, i, k, f, r);
+        uint32_t j = mulshift(r[0], i + 1);
+        uint32_t t = order[i]; order[i] = order[j]; order[j] = t;
+    }
+    uint32_t n = 0;
+    for (uint32_t a = 0; a < G; ++a) {
+        uint32_t g = order[a], cnt = 0;
+        for (uint32_t m = 0; m < M; ++m)
+            if (((uint64_t)f * M + m) % G == g) members[cnt++] = m;
+        for (uint32_t i = cnt - 1; i >= 1 && cnt > 1; --i) {
+            uint32_t r[4];
+            draw(seed, TAG_RING, 2 + g, i, k, f, r);
+            uint32_t j = mulshift(r[0], i + 1);
+            uint32_t t = members[i]; members[i] = members[j]; members[j] = t;
+        }
+        for (uint32_t i = 0; i < cnt; ++i) p[n++] = members[i];
+    }
+    for (uint32_t t = 0; t < M; ++t) {
+        uint32_t here = p[t];
+        if (pi) pi[t] = here;
+        if (succ) succ[here] = p[(t + 1) % M];
+        if (pred) pred[here] = p[(t + M - 1) % M];
+    }
+    free(order); free(members); free(p);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Step 2 (Alg. 3; Eq. 3 and Eq. 4): number of particles to exchange.        */
 /* P holds the integer PE masses of the previous iteration.                  */
@@ -237,6 +284,7 @@ typedef struct {
     double psf_sigma, background, noise_sigma;
     double q, sigma_I;
     uint64_t seed;
+    uint32_t ring_groups;   /* ARNA: > 1 selects the hardware-aware ring */
 } orc_config;
 
 typedef struct { double x, y, vx, vy, I; } particle;
@@ -500,7 +548,10 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
         const double *Lprev = o->L + (size_t)f * M;
 
         /* 1: ring for this iteration. */
-        orc_ring(c->seed, f, k, M, c->mode, pi, pred, NULL);
+        if (c->mode == ORC_MODE_ARNA && c->ring_groups > 1)
+            orc_ring_groups(c->seed, f, k, M, c->ring_groups, pi, pred, NULL);
+        else
+            orc_ring(c->seed, f, k, M, c->mode, pi, pred, NULL);
 
         /* 2: exchange ratio from the previous iteration's PE masses. */
         pe_masses(Lprev, M, Pprev);
@@ -844,7 +895,10 @@ static int run_frozen(const orc_config *cfg, const double *truth, double dI0,
         for (uint32_t f = 0; f < F; ++f) {
             const double *Lf = L + (size_t)f * M;
             const double *dLf = dL + (size_t)f * M * NTH;
-            orc_ring(cfg->seed, f, k, M, cfg->mode, pi, pred, NULL);
+            if (cfg->mode == ORC_MODE_ARNA && cfg->ring_groups > 1)
+                orc_ring_groups(cfg->seed, f, k, M, cfg->ring_groups, pi, pred, NULL);
+            else
+                orc_ring(cfg->seed, f, k, M, cfg->mode, pi, pred, NULL);
             uint32_t nex;
             if (record) {
                 pe_masses(Lf, M, P);

@@ -58,7 +58,7 @@ class _Config(ctypes.Structure):
         ("eff_cutoff", ctypes.c_double),
         ("psf_sigma", ctypes.c_double), ("background", ctypes.c_double),
         ("noise_sigma", ctypes.c_double), ("q", ctypes.c_double), ("sigma_I", ctypes.c_double),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("ring_groups", ctypes.c_uint32),
     ]
 
 
@@ -87,6 +87,7 @@ def _declare(L):
     P32 = ctypes.POINTER(ctypes.c_uint32)
     L.orc_philox.argtypes = [P32, P32, P32]
     L.orc_ring.argtypes = [u64, u32, u32, u32, i32, P32, P32, P32]
+    L.orc_ring_groups.argtypes = [u64, u32, u32, u32, u32, P32, P32, P32]
     L.orc_fixed_nex.argtypes = [ctypes.c_double, u32]
     L.orc_fixed_nex.restype = u32
     L.orc_nex.argtypes = [P32, u32, u32, i32, ctypes.c_double, ctypes.c_double,
@@ -151,6 +152,16 @@ def ring(seed: int, f: int, k: int, M: int, mode: int = MODE_ARNA):
     succ = np.zeros(M, np.uint32)
     lib().orc_ring(seed, f, k, M, mode, _p(pi, ctypes.c_uint32), _p(pred, ctypes.c_uint32),
                    _p(succ, ctypes.c_uint32))
+    return pi, pred, succ
+
+
+def ring_groups(seed: int, f: int, k: int, M: int, G: int):
+    """Hardware-aware ring: PE m of filter f in group (f M + m) mod G."""
+    pi = np.zeros(M, np.uint32)
+    pred = np.zeros(M, np.uint32)
+    succ = np.zeros(M, np.uint32)
+    lib().orc_ring_groups(seed, f, k, M, G, _p(pi, ctypes.c_uint32), _p(pred, ctypes.c_uint32),
+                          _p(succ, ctypes.c_uint32))
     return pi, pred, succ
 
 
@@ -241,6 +252,7 @@ class OracleConfig:
     q: float = 0.5
     sigma_I: float = 0.5
     seed: int = 1
+    ring_groups: int = 0
     extra: dict = field(default_factory=dict)
 
     @classmethod
@@ -255,7 +267,8 @@ class OracleConfig:
                        _f32(self.fixed_ratio), _f32(self.initial_ratio), _f32(self.eff_cutoff),
                        _f32(self.psf_sigma) if psf_sigma is None else float(psf_sigma),
                        _f32(self.background), _f32(self.noise_sigma),
-                       _f32(self.q) if q is None else float(q), _f32(self.sigma_I), self.seed)
+                       _f32(self.q) if q is None else float(q), _f32(self.sigma_I), self.seed,
+                       self.ring_groups)
 
     @property
     def N(self) -> int:

@@ -40,6 +40,7 @@ class pf_config(ctypes.Structure):
         ("psf_sigma", ctypes.c_float), ("background", ctypes.c_float),
         ("noise_sigma", ctypes.c_float), ("q", ctypes.c_float), ("sigma_I", ctypes.c_float),
         ("debug", ctypes.c_uint32),
+        ("ring_groups", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]
@@ -95,7 +96,7 @@ SIGNATURES = {
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                     _U32P]),
     "pf_debug_ring": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                     ctypes.c_uint32, ctypes.c_uint32, _P]),
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P]),
     "pf_debug_philox": (ctypes.c_int, [_P, _P, ctypes.c_uint32, _P]),
 }
 

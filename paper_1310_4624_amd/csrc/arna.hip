@@ -203,6 +203,7 @@ int validate(const pf_config *c) {
     if (c->n_filters == 0 || c->n_pe == 0 || c->n_per_pe == 0) return PF_EINVAL;
     if (c->n_pe > PF_MAX_PE || c->n_per_pe > PF_MAX_PER_PE) return PF_EUNSUPPORTED;
     if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
+    if (c->ring_groups > 256) return PF_EINVAL;
     if (c->lik_mode == PF_LIK_POISSON && !(c->background > 0.f)) return PF_EINVAL;
     if (c->lik_mode != PF_LIK_POINT) {
         if (c->patch == 0 || (c->patch & 1u) == 0) return PF_EINVAL;
@@ -245,8 +246,8 @@ int ensure_ring(pf_ctx *c, uint64_t k, bool downward = false) {
     const uint64_t base = (downward && k >= kRingSteps) ? k - (kRingSteps - 1) : (downward ? 1 : k);
     const uint32_t M = c->cfg.n_pe;
     hipLaunchKernelGGL(k_ring, dim3(kRingSteps, c->cfg.n_filters), dim3(256),
-                       2 * M * sizeof(uint16_t), c->stream, c->ring_tab, (uint32_t)base,
-                       c->cfg.n_filters, M, c->key0, c->key1);
+                       ring_lds_bytes(M, c->cfg.ring_groups), c->stream, c->ring_tab,
+                       (uint32_t)base, c->cfg.n_filters, M, c->cfg.ring_groups, c->key0, c->key1);
     HIP_OK(hipGetLastError());
     c->ring_base = base;
     c->ring_valid = true;
@@ -914,8 +915,8 @@ int pf_debug_nex(const uint32_t *p, uint32_t M, uint32_t n_p, uint32_t mode, flo
 }
 
 int pf_debug_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t mode,
-                  uint32_t *pred_out) {
-    if (!pred_out || M == 0 || M > PF_MAX_PE) return PF_EINVAL;
+                  uint32_t groups, uint32_t *pred_out) {
+    if (!pred_out || M == 0 || M > PF_MAX_PE || groups > 256) return PF_EINVAL;
     if (mode != PF_MODE_ARNA || M == 1) {
         for (uint32_t m = 0; m < M; ++m) pred_out[m] = (m + M - 1) % M;
         return PF_OK;
@@ -924,8 +925,8 @@ int pf_debug_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t mo
     uint16_t *dt = nullptr;
     int rc = dev_alloc(&dt, (size_t)(f + 1) * M);
     if (rc != PF_OK) return rc;
-    hipLaunchKernelGGL(k_ring, dim3(1, f + 1), dim3(256), 2 * M * sizeof(uint16_t), 0, dt, k,
-                       f + 1, M, (uint32_t)seed, (uint32_t)(seed >> 32));
+    hipLaunchKernelGGL(k_ring, dim3(1, f + 1), dim3(256), ring_lds_bytes(M, groups), 0, dt, k,
+                       f + 1, M, groups, (uint32_t)seed, (uint32_t)(seed >> 32));
     uint16_t *h = (uint16_t *)malloc((size_t)M * 2);
     if (!h) rc = PF_ENOMEM;
     if (rc == PF_OK &&

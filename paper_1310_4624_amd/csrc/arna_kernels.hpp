@@ -665,25 +665,102 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
 // Step 1 for kRingSteps iterations at once: Fisher-Yates (Durstenfeld,
 // i = M-1 .. 1, j = floor(r_i (i + 1) / 2^32)) over the M labels; the ring
 // visits perm[0], perm[1], ... and closes.  Grid (steps, F).
+// With G > 1 groups (the hardware-aware ring of Sec. VI) PE m belongs to group
+// (f M + m) mod G -- with G = 8 the accelerator die its workgroup runs on,
+// since workgroups are dealt to the dies round-robin -- and the ring visits
+// the groups in a shuffled order (draws Philox(i, k, f, RING | 1)), the
+// members of each group, taken in increasing m, in a shuffled order (draws
+// Philox(i, k, f, RING | 2 + g)); only G of its M edges join different groups.
+// Dynamic LDS: ring_lds_bytes(M, G).
+__host__ __device__ constexpr size_t ring_lds_bytes(uint32_t M, uint32_t G) {
+    return 4 * (size_t)M + (G > 1 ? 12 * (size_t)G : 0) + 16;
+}
 __global__ __launch_bounds__(256) void k_ring(uint16_t *tab, uint32_t base, uint32_t F,
-                                              uint32_t M, uint32_t key0, uint32_t key1) {
+                                              uint32_t M, uint32_t G, uint32_t key0,
+                                              uint32_t key1) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *perm = (uint16_t *)smem;
     uint16_t *jd = perm + M;
     const uint32_t k = base + blockIdx.x, f = blockIdx.y;
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-        perm[i] = (uint16_t)i;
-        jd[i] = (i == 0) ? 0 : (uint16_t)mulshift(philox(i, k, f, kTagRing << 24, key0, key1).x,
+    if (G <= 1) {
+        for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
+            perm[i] = (uint16_t)i;
+            jd[i] = (i == 0) ? 0
+                             : (uint16_t)mulshift(philox(i, k, f, kTagRing << 24, key0, key1).x,
                                                   i + 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (uint32_t i = M - 1; i >= 1; --i) {
-            const uint32_t j = jd[i];
-            const uint16_t t = perm[i];
-            perm[i] = perm[j];
-            perm[j] = t;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (uint32_t i = M - 1; i >= 1; --i) {
+                const uint32_t j = jd[i];
+                const uint16_t t = perm[i];
+                perm[i] = perm[j];
+                perm[j] = t;
+            }
+        }
+    } else {
+        uint32_t *gbase = (uint32_t *)(jd + M);   // start of group g, natural order
+        uint32_t *pbase = gbase + G;               // start of group g along the ring
+        uint16_t *order = (uint16_t *)(pbase + G);
+        // PE m is in group (r0 + m mod G) mod G and is member number m / G of
+        // it; group (r0 + d) mod G has q + (d < rem) members
+        const uint32_t r0 = (uint32_t)(((uint64_t)f * M) % G);
+        const uint32_t q = M / G, rem = M % G;
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (uint32_t g = 0; g < G; ++g) {
+                gbase[g] = acc;
+                acc += q + (((g + G - r0) % G) < rem ? 1u : 0u);
+            }
+        }
+        for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) order[g] = (uint16_t)g;
+        __syncthreads();
+        for (uint32_t m = threadIdx.x; m < M; m += blockDim.x) {
+            const uint32_t g = (r0 + m % G) % G, idx = m / G;
+            perm[gbase[g] + idx] = (uint16_t)m;
+            jd[gbase[g] + idx] =
+                (idx == 0) ? 0
+                           : (uint16_t)mulshift(
+                                 philox(idx, k, f, (kTagRing << 24) | (2u + g), key0, key1).x,
+                                 idx + 1);
+        }
+        __syncthreads();
+        // shuffle every group's members (one thread per group), then the
+        // order of the groups
+        for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) {
+            const uint32_t cnt = q + (((g + G - r0) % G) < rem ? 1u : 0u);
+            uint16_t *seg = perm + gbase[g];
+            const uint16_t *js = jd + gbase[g];
+            for (uint32_t i = cnt - 1; i >= 1 && cnt > 1; --i) {
+                const uint32_t j = js[i];
+                const uint16_t t = seg[i];
+                seg[i] = seg[j];
+                seg[j] = t;
+            }
+        }
+        if (threadIdx.x == 0) {
+            for (uint32_t i = G - 1; i >= 1; --i) {
+                const uint32_t j = mulshift(philox(i, k, f, (kTagRing << 24) | 1u, key0, key1).x,
+                                            i + 1);
+                const uint16_t t = order[i];
+                order[i] = order[j];
+                order[j] = t;
+            }
+            uint32_t acc = 0;
+            for (uint32_t a = 0; a < G; ++a) {
+                const uint32_t g = order[a];
+                pbase[g] = acc;
+                acc += q + (((g + G - r0) % G) < rem ? 1u : 0u);
+            }
+        }
+        __syncthreads();
+        // the groups in ring order (jd is free now), then back into perm
+        for (uint32_t m = threadIdx.x; m < M; m += blockDim.x) {
+            const uint32_t g = (r0 + m % G) % G, idx = m / G;
+            jd[pbase[g] + idx] = perm[gbase[g] + idx];
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) perm[i] = jd[i];
     }
     __syncthreads();
     uint16_t *out = tab + ((size_t)blockIdx.x * F + f) * M;

@@ -34,11 +34,13 @@ def _frames(seq):
 
 
 def infoshare(mode: str, seq_seed: int = 1000, filter_seed: int = 1, n_pe: int = 256,
-              n_per_pe: int = 4096, steps: int = 200, radius: float = 2.0, seq=None) -> dict:
+              n_per_pe: int = 4096, steps: int = 200, radius: float = 2.0, seq=None,
+              ring_groups: int = 0) -> dict:
     wl = "arna_infoshare_512_256x4096"
     mflag, ratio = MODES[mode]
     cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, initial_ratio=0.1,
-                              n_pe=n_pe, n_per_pe=n_per_pe, seed=filter_seed)
+                              n_pe=n_pe, n_per_pe=n_per_pe, seed=filter_seed,
+                              ring_groups=ring_groups)
     seq = seq if seq is not None else synth.make_sequence(wl, seed=seq_seed, frames=steps)
     frames = _frames(seq)
     tr = Tracker(cfg, seq.initial_truth()[:1])
@@ -57,6 +59,7 @@ def infoshare(mode: str, seq_seed: int = 1000, filter_seed: int = 1, n_pe: int =
             converged_at = k
     tr.close()
     return dict(mode=mode, n_pe=n_pe, n_per_pe=n_per_pe, seq_seed=seq_seed,
+                ring_groups=ring_groups,
                 filter_seed=filter_seed, steps=len(within), converged_at=converged_at,
                 fraction_within=within, pe_eff_over_m=pe_eff, n_ex=n_ex)
 
@@ -111,6 +114,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling"])
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
+    ap.add_argument("--ring-groups", type=int, default=0)
     ap.add_argument("--modes", default="arna,rna10,rna50,rna0")
     ap.add_argument("--seeds", type=int, default=1)
     ap.add_argument("--n-pe", type=int, default=256)
@@ -124,7 +128,8 @@ def main():
             for s in range(args.seeds):
                 for mode in args.modes.split(","):
                     r = infoshare(mode, seq_seed=1000 + s, filter_seed=1 + s, n_pe=n_pe,
-                                  n_per_pe=args.n_per_pe, steps=args.steps or 40)
+                                  n_per_pe=args.n_per_pe, steps=args.steps or 40,
+                                  ring_groups=args.ring_groups)
                     r["pe_eff_over_m_at"] = {str(i): r["pe_eff_over_m"][i - 1]
                                              for i in (1, 2, 5, 10, 20, 40)
                                              if i <= len(r["pe_eff_over_m"])}
@@ -153,7 +158,8 @@ def main():
         for mode in args.modes.split(","):
             if args.what == "infoshare":
                 r = infoshare(mode, seq_seed=1000 + s, filter_seed=1 + s, n_pe=args.n_pe,
-                              n_per_pe=args.n_per_pe, steps=args.steps or 200)
+                              n_per_pe=args.n_per_pe, steps=args.steps or 200,
+                              ring_groups=args.ring_groups)
                 if not args.curves:
                     r = {k: v for k, v in r.items()
                          if k not in ("fraction_within", "pe_eff_over_m", "n_ex")} | {

@@ -11,12 +11,12 @@ from . import _native as nat
 
 CONFIG_KEYS = ("n_filters", "n_pe", "n_per_pe", "width", "height", "patch", "mode",
                "init_mode", "lik_mode", "fixed_ratio", "initial_ratio", "eff_cutoff",
-               "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed")
+               "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed", "ring_groups")
 
 DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
                 mode=nat.PF_MODE_RNA, init_mode=nat.PF_INIT_TRACKING, lik_mode=nat.PF_LIK_PATCH,
                 fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
-                background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1)
+                background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1, ring_groups=0)
 
 
 def _ptr(a: np.ndarray):
@@ -252,9 +252,10 @@ def nex(P, n_p: int, mode: int = nat.PF_MODE_ARNA, fixed_ratio: float = 0.1,
     return int(out.value)
 
 
-def ring(seed: int, f: int, k: int, M: int, mode: int = nat.PF_MODE_ARNA) -> np.ndarray:
+def ring(seed: int, f: int, k: int, M: int, mode: int = nat.PF_MODE_ARNA,
+         groups: int = 0) -> np.ndarray:
     pred = np.zeros(M, np.uint32)
-    nat.check(nat.lib().pf_debug_ring(seed, f, k, M, mode, _ptr(pred)), "pf_debug_ring")
+    nat.check(nat.lib().pf_debug_ring(seed, f, k, M, mode, groups, _ptr(pred)), "pf_debug_ring")
     return pred
 
 

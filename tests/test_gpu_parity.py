@@ -103,6 +103,17 @@ def test_device_ring_bit_exact(M):
     assert np.array_equal(p.ring(SEED, 0, 5, M, mode=0), (np.arange(M) - 1) % M)
 
 
+@pytest.mark.parametrize("M,G", [(2, 8), (7, 8), (8, 8), (64, 8), (256, 8), (1000, 8), (300, 3),
+                                 (4096, 256), (100, 100), (8192, 7)])
+def test_device_grouped_ring_bit_exact(M, G):
+    p = pf()
+    for f in [0, 1, 5]:
+        for k in [1, 64, 777]:
+            got = p.ring(SEED, f, k, M, groups=G)
+            _, want, _ = orc.ring_groups(SEED, f, k, M, G)
+            assert np.array_equal(got, want), (M, G, f, k)
+
+
 # ------------------------------------------------------- one-step float parity
 def seeded_case(name):
     rng = np.random.Generator(np.random.PCG64(zlib.crc32(name.encode())))
@@ -126,6 +137,15 @@ def seeded_case(name):
                    sigma_I=0.5, seed=SEED + 2)
         truth = np.array([[[64.2, 63.9, 0, 0, 8.0]]])
         frame = synth.render(truth[0], 128, 128, 1.5, 5.0, 2.0, rng)
+        centre = truth[0, :, :2]
+    elif name == "arna_groups_2x24x300":
+        # hardware-aware ring: 8 groups
+        cfg = dict(n_filters=2, n_pe=24, n_per_pe=300, width=96, height=80, patch=9,
+                   mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 6, ring_groups=8)
+        truth = np.array([[[30.3, 40.7, 0, 0, 12.0], [70.6, 20.2, 0, 0, 9.0]]])
+        frame = synth.render(truth[0], 96, 80, 1.5, 5.0, 2.0, rng)
         centre = truth[0, :, :2]
     elif name == "poisson_arna_1x4x1000":
         cfg = dict(n_filters=1, n_pe=4, n_per_pe=1000, width=64, height=48, patch=9,
@@ -179,7 +199,8 @@ def run_one_step(cfg, frame, state, logmass, k_done):
 
 
 @pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
-                                  "poisson_arna_1x4x1000", "arna_2x2100x4", "point_rna_3x5x77"])
+                                  "poisson_arna_1x4x1000", "arna_2x2100x4", "arna_groups_2x24x300",
+                                  "point_rna_3x5x77"])
 @pytest.mark.parametrize("k_done", [0, 7])
 def test_one_step_parity(name, k_done):
     cfg, frame, state, logmass = seeded_case(name)
