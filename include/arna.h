@@ -89,6 +89,11 @@ typedef struct {
                                  * workgroup runs on -- and the ring visits the groups in
                                  * a random order and each group's PEs in a random order,
                                  * so only G of its M edges join different groups */
+    uint32_t block_size;        /* threads per workgroup (one workgroup per PE): 0 = the
+                                 * default (N_p rounded up to 64, at most 1024); else a
+                                 * multiple of 64 in 64..1024 with block_size * P >= N_p
+                                 * for P = 1, 2 or 4 slots per thread (the smallest such P
+                                 * is used) -- the knob of the autotuner */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;
@@ -149,6 +154,28 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map);
  * estimate, W, PE_eff, N_ex, log-likelihood increment).  Returns PF_ENUMERIC
  * if any iteration so far produced a NaN log-weight (the flag is sticky). */
 int pf_estimate(pf_ctx *c, pf_estimate_t *out);
+
+/* -------------------------------------------------------------- batches */
+/* Many independent filters advanced together: every iteration of
+ * pf_batch_run issues one launch per group of contexts that share the kernel
+ * variant (slots per thread, workgroup size, the 9 x 9 patch with Gaussian or
+ * Poisson noise, or point data) instead of one launch per context; the work
+ * of each workgroup is exactly that of pf_step, so the results are bitwise
+ * those of separate pf_run calls.  Contexts of other patch sizes are stepped
+ * one by one inside the same run.  The contexts must use one stream and stay
+ * alive until pf_batch_destroy; the batch owns only its launch tables. */
+typedef struct pf_batch pf_batch;
+int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out);
+
+/* n_steps iterations of every context: context i takes its frames from
+ * d_frames[i] + s * frame_stride[i] (host arrays of n device pointers and
+ * strides in floats).  use_graph != 0 captures the whole run into one HIP
+ * graph, launches it and synchronizes the stream; otherwise the launches are
+ * only enqueued (the call still synchronizes once, before uploading the
+ * run's argument table).  PF_ESTATE if a context is recording a gradient. */
+int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                 uint32_t n_steps, int use_graph);
+void pf_batch_destroy(pf_batch *b);
 
 /* ------------------------------------------------------------- gradient */
 /* The filter's estimate of the log marginal likelihood of a run of K

@@ -7,4 +7,4 @@ the GPU.
 from ._native import (PF_INIT_INFOSHARE, PF_INIT_TRACKING, PF_LIK_PATCH, PF_LIK_POINT,  # noqa: F401
                       PF_LIK_POISSON,
                       PF_MODE_ARNA, PF_MODE_RNA, PF_DEBUG_LINEAGE, PF_DEBUG_TRACE, PFError)
-from .tracker import Tracker, nex, philox, resample_q, ring  # noqa: F401
+from .tracker import Batch, Tracker, nex, philox, resample_q, ring  # noqa: F401

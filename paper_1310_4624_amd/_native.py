@@ -41,6 +41,7 @@ class pf_config(ctypes.Structure):
         ("noise_sigma", ctypes.c_float), ("q", ctypes.c_float), ("sigma_I", ctypes.c_float),
         ("debug", ctypes.c_uint32),
         ("ring_groups", ctypes.c_uint32),
+        ("block_size", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]
@@ -83,6 +84,9 @@ SIGNATURES = {
     "pf_estimate": (ctypes.c_int, [_P, ctypes.POINTER(pf_estimate_t)]),
     "pf_destroy": (None, [_P]),
     "pf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pf_batch_create": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "pf_batch_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, ctypes.c_int]),
+    "pf_batch_destroy": (None, [_P]),
     "pf_grad_begin": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "pf_grad_end": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "pf_grad_value": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),

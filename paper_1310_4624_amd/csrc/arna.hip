@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "arna.h"
 #include "arna_device.hpp"
@@ -102,6 +103,24 @@ struct pf_ctx {
     Lik lik;
 };
 
+struct pf_batch {
+    struct Group {
+        void *fn;
+        uint32_t ppt, block, blocks;
+        size_t lds;
+        std::vector<uint32_t> members;   // context indices
+        std::vector<uint32_t> first;     // first workgroup of each member, then the total
+        uint32_t *d_first;
+    };
+    std::vector<pf_ctx *> ctx;
+    std::vector<Group> groups;
+    std::vector<uint32_t> solo;          // contexts launched one by one
+    uint32_t n_batched;
+    hipStream_t stream;
+    StepArgs *d_args;                    // [steps][n_batched], grown on demand
+    size_t args_cap;
+};
+
 namespace {
 
 // From this many PEs per filter on, the master step is computed once per
@@ -157,6 +176,8 @@ void *pick_patch_kernel(uint32_t ppt, uint32_t half) {
     }
     if (ppt == 1) {
         ARNA_HALVES(1)
+    } else if (ppt == 2) {
+        ARNA_HALVES(2)
     } else {
         ARNA_HALVES(4)
     }
@@ -166,9 +187,31 @@ void *pick_patch_kernel(uint32_t ppt, uint32_t half) {
 
 void *pick_step_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
     if (lik_mode == PF_LIK_POINT)
-        return ppt == 1 ? step_kernel<1, 0, kLikPoint>() : step_kernel<4, 0, kLikPoint>();
+        return ppt == 1 ? step_kernel<1, 0, kLikPoint>()
+                        : (ppt == 2 ? step_kernel<2, 0, kLikPoint>() : step_kernel<4, 0, kLikPoint>());
     if (lik_mode == PF_LIK_POISSON) return pick_patch_kernel<kLikPoisson>(ppt, half);
     return pick_patch_kernel<kLikGauss>(ppt, half);
+}
+
+// Batched variants exist for the paper's 9 x 9 patch (Gaussian or Poisson
+// noise) and for point observations; other contexts of a batch are launched
+// one by one.
+template <int PPT, int HALF, int LIK>
+void *batch_kernel() {
+    return reinterpret_cast<void *>(&k_step_batch<PPT, HALF, LIK>);
+}
+
+template <int HALF, int LIK>
+void *batch_kernel_ppt(uint32_t ppt) {
+    return ppt == 1 ? batch_kernel<1, HALF, LIK>()
+                    : (ppt == 2 ? batch_kernel<2, HALF, LIK>() : batch_kernel<4, HALF, LIK>());
+}
+
+void *pick_batch_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT) return batch_kernel_ppt<0, kLikPoint>(ppt);
+    if (half != 4) return nullptr;
+    if (lik_mode == PF_LIK_POISSON) return batch_kernel_ppt<4, kLikPoisson>(ppt);
+    return batch_kernel_ppt<4, kLikGauss>(ppt);
 }
 
 template <int PPT, int HALF>
@@ -191,6 +234,8 @@ void *pick_adjoint_kernel(uint32_t ppt, uint32_t half) {
     }
     if (ppt == 1) {
         ARNA_ADJ_HALVES(1)
+    } else if (ppt == 2) {
+        ARNA_ADJ_HALVES(2)
     } else {
         ARNA_ADJ_HALVES(4)
     }
@@ -204,6 +249,10 @@ int validate(const pf_config *c) {
     if (c->n_pe > PF_MAX_PE || c->n_per_pe > PF_MAX_PER_PE) return PF_EUNSUPPORTED;
     if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
     if (c->ring_groups > 256) return PF_EINVAL;
+    if (c->block_size) {
+        if (c->block_size % 64 || c->block_size > 1024) return PF_EINVAL;
+        if ((uint64_t)c->block_size * 4 < c->n_per_pe) return PF_EINVAL;
+    }
     if (c->lik_mode == PF_LIK_POISSON && !(c->background > 0.f)) return PF_EINVAL;
     if (c->lik_mode != PF_LIK_POINT) {
         if (c->patch == 0 || (c->patch & 1u) == 0) return PF_EINVAL;
@@ -240,18 +289,31 @@ void free_all(pf_ctx *c) {
 // Ring table for iteration k; when it has to be rebuilt, the batch of
 // kRingSteps iterations starts at k (forward runs) or ends at k (the adjoint
 // sweep, which runs backwards).
-int ensure_ring(pf_ctx *c, uint64_t k, bool downward = false) {
-    if (c->cfg.mode != PF_MODE_ARNA || c->cfg.n_pe <= 1) return PF_OK;
-    if (c->ring_valid && k >= c->ring_base && k < c->ring_base + kRingSteps) return PF_OK;
-    const uint64_t base = (downward && k >= kRingSteps) ? k - (kRingSteps - 1) : (downward ? 1 : k);
+// Whether iteration k needs the ring table rebuilt; if so the new batch's
+// first iteration goes to *base and the context records it as built.
+bool plan_ring(pf_ctx *c, uint64_t k, bool downward, uint64_t *base) {
+    if (c->cfg.mode != PF_MODE_ARNA || c->cfg.n_pe <= 1) return false;
+    if (c->ring_valid && k >= c->ring_base && k < c->ring_base + kRingSteps) return false;
+    *base = (downward && k >= kRingSteps) ? k - (kRingSteps - 1) : (downward ? 1 : k);
+    c->ring_base = *base;
+    c->ring_valid = true;
+    return true;
+}
+
+int launch_ring(pf_ctx *c, uint64_t base) {
     const uint32_t M = c->cfg.n_pe;
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_ring, dim3(kRingSteps, c->cfg.n_filters), dim3(256),
                        ring_lds_bytes(M, c->cfg.ring_groups), c->stream, c->ring_tab,
                        (uint32_t)base, c->cfg.n_filters, M, c->cfg.ring_groups, c->key0, c->key1);
     HIP_OK(hipGetLastError());
-    c->ring_base = base;
-    c->ring_valid = true;
     return PF_OK;
+}
+
+int ensure_ring(pf_ctx *c, uint64_t k, bool downward = false) {
+    uint64_t base;
+    if (!plan_ring(c, k, downward, &base)) return PF_OK;
+    return launch_ring(c, base);
 }
 
 StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
@@ -307,11 +369,22 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
 // state load), when the context uses them.
 int refresh_master(pf_ctx *c, int which) {
     if (!c->mrec[0]) return PF_OK;
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(256), 0, c->stream,
                        c->rec[which], c->mrec[which], c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
                        c->fixed_nex, c->cutoff_ppm);
     HIP_OK(hipGetLastError());
     return PF_OK;
+}
+
+// Host state after iteration k has been enqueued.
+void advance(pf_ctx *c, uint64_t k) {
+    c->cur = 1 - c->cur;
+    if (c->g_cap) ++c->g_len;
+    c->force_anc = nullptr;
+    c->force_nex = nullptr;
+    c->step = k;
+    c->exchanged = false;
 }
 
 int launch_step(pf_ctx *c, const float *frame) {
@@ -325,12 +398,7 @@ int launch_step(pf_ctx *c, const float *frame) {
     if (!fn) return PF_EUNSUPPORTED;
     void *args[] = {&a};
     HIP_OK(hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(c->block), args, c->lds, c->stream));
-    c->cur = 1 - c->cur;
-    if (c->g_cap) ++c->g_len;
-    c->force_anc = nullptr;
-    c->force_nex = nullptr;
-    c->step = k;
-    c->exchanged = false;
+    advance(c, k);
     return PF_OK;
 }
 
@@ -365,8 +433,13 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     const uint32_t F = cfg->n_filters, M = cfg->n_pe, np = cfg->n_per_pe;
     c->FM = (uint64_t)F * M;
     c->N = c->FM * np;
-    c->block = block_of(np);
-    c->ppt = np > 1024 ? 4 : 1;
+    if (cfg->block_size) {
+        c->block = cfg->block_size;
+        c->ppt = np <= c->block ? 1 : (np <= 2 * c->block ? 2 : 4);
+    } else {
+        c->block = block_of(np);
+        c->ppt = np > 1024 ? 4 : 1;
+    }
     c->half = cfg->lik_mode != PF_LIK_POINT ? cfg->patch / 2 : 0;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
@@ -454,6 +527,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     }
     if (rc == PF_OK) {
         const uint64_t work = N > c->FM ? N : c->FM;
+        (void)hipGetLastError();   // clear errors of earlier, unrelated calls
         hipLaunchKernelGGL(k_init, dim3((uint32_t)((work + 255) / 256)), dim3(256), 0, c->stream,
                            c->prop[0], c->anc[0], c->rec[0], c->lin[0], d_truth, N, M, np,
                            cfg->width,
@@ -525,6 +599,7 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map) {
     if (rc != PF_OK) return rc;
     if (d_src_map) {
         StepArgs a = make_args(c, k, nullptr);
+        (void)hipGetLastError();   // clear errors of earlier, unrelated calls
         hipLaunchKernelGGL(k_exchange_map, dim3((uint32_t)c->FM), dim3(256), 0, c->stream, a,
                            d_src_map);
         HIP_OK(hipGetLastError());
@@ -536,6 +611,7 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map) {
 int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
     if (!c || !o) return PF_EINVAL;
     const uint32_t F = c->cfg.n_filters, M = c->cfg.n_pe;
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_global, dim3(F), dim3(256), 0, c->stream, cur_rec(c), c->est, M,
                        c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex, c->cutoff_ppm);
     HIP_OK(hipGetLastError());
@@ -645,6 +721,7 @@ int pf_grad_value(pf_ctx *c, double *host_J) {
     if (!c || !host_J) return PF_EINVAL;
     if (!c->g_cap) return PF_ESTATE;
     const uint32_t F = c->cfg.n_filters;
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, c->g_len,
                        (const double *)nullptr, c->cfg.n_pe, c->cfg.n_per_pe, (uint32_t)c->FM,
                        c->g_out);
@@ -718,6 +795,7 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
                 rc = PF_EHIP;
         }
         if (rc == PF_OK) {
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
             hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, K,
                                (const double *)c->g_theta, c->cfg.n_pe, c->cfg.n_per_pe,
                                (uint32_t)FM, c->g_out);
@@ -739,6 +817,206 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
     c->g_cap = 0;
     c->g_len = 0;
     return rc;
+}
+
+int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
+    if (!out) return PF_EINVAL;
+    *out = nullptr;
+    if (!ctxs || n == 0) return PF_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!ctxs[i] || ctxs[i]->stream != ctxs[0]->stream) return PF_EINVAL;
+        for (uint32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return PF_EINVAL;
+    }
+    pf_batch *b = new (std::nothrow) pf_batch();
+    if (!b) return PF_ENOMEM;
+    b->ctx.assign(ctxs, ctxs + n);
+    b->stream = ctxs[0]->stream;
+    b->n_batched = 0;
+    b->d_args = nullptr;
+    b->args_cap = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        pf_ctx *c = ctxs[i];
+        void *fn = pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
+        if (!fn || c->FM > 0xFFFFFFFFull) {
+            b->solo.push_back(i);
+            continue;
+        }
+        pf_batch::Group *g = nullptr;
+        for (auto &h : b->groups)
+            if (h.fn == fn && h.block == c->block) g = &h;
+        if (!g) {
+            b->groups.push_back(pf_batch::Group{fn, c->ppt, c->block, 0, 0, {}, {}, nullptr});
+            g = &b->groups.back();
+        }
+        g->members.push_back(i);
+        if (c->lds > g->lds) g->lds = c->lds;
+    }
+    int rc = PF_OK;
+    for (auto &g : b->groups) {
+        uint64_t acc = 0;
+        for (uint32_t i : g.members) {
+            g.first.push_back((uint32_t)acc);
+            acc += b->ctx[i]->FM;
+        }
+        if (acc > 0x7FFFFFFFull) rc = PF_EUNSUPPORTED;
+        g.blocks = (uint32_t)acc;
+        g.first.push_back((uint32_t)acc);
+        b->n_batched += (uint32_t)g.members.size();
+        if (rc == PF_OK) rc = dev_alloc(&g.d_first, g.first.size());
+        if (rc == PF_OK &&
+            hipMemcpy(g.d_first, g.first.data(), g.first.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            rc = PF_EHIP;
+        if (rc == PF_OK && hipFuncSetAttribute(g.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)g.lds) != hipSuccess)
+            rc = PF_EHIP;
+    }
+    if (rc != PF_OK) {
+        pf_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PF_OK;
+}
+
+int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                 uint32_t n_steps, int use_graph) {
+    if (!b || !d_frames || !frame_stride) return PF_EINVAL;
+    const uint32_t n = (uint32_t)b->ctx.size();
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!d_frames[i] && n_steps) return PF_EINVAL;
+        if (b->ctx[i]->g_cap) return PF_ESTATE;   // recording runs one context at a time
+        if (b->ctx[i]->step + n_steps > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
+    }
+    if (n_steps == 0) return PF_OK;
+    const uint32_t nb = b->n_batched;
+    // host pass: every batched context's arguments for every iteration, and
+    // the ring tables each iteration has to rebuild first (rings[i]: context,
+    // first iteration of the new table)
+    std::vector<StepArgs> args((size_t)n_steps * nb);
+    std::vector<std::vector<std::pair<uint32_t, uint64_t>>> rings(n_steps);
+    std::vector<int> saved_cur(n);
+    std::vector<uint64_t> saved_step(n), saved_base(n);
+    std::vector<bool> saved_valid(n);
+    std::vector<const uint32_t *> saved_fa(n), saved_fn(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        pf_ctx *c = b->ctx[i];
+        saved_cur[i] = c->cur;
+        saved_step[i] = c->step;
+        saved_base[i] = c->ring_base;
+        saved_valid[i] = c->ring_valid;
+        saved_fa[i] = c->force_anc;
+        saved_fn[i] = c->force_nex;
+    }
+    for (uint32_t t = 0; t < n_steps; ++t) {
+        uint32_t slot = 0;
+        for (auto &g : b->groups)
+            for (uint32_t i : g.members) {
+                pf_ctx *c = b->ctx[i];
+                const uint64_t k = c->step + 1;
+                uint64_t base;
+                if (plan_ring(c, k, false, &base)) rings[t].push_back({i, base});
+                args[(size_t)t * nb + slot++] =
+                    make_args(c, k, d_frames[i] + (size_t)t * frame_stride[i]);
+                advance(c, k);
+            }
+    }
+    // the enqueue pass replays the same state changes
+    auto restore = [&]() {
+        for (uint32_t i = 0; i < n; ++i) {
+            pf_ctx *c = b->ctx[i];
+            c->cur = saved_cur[i];
+            c->step = saved_step[i];
+            c->ring_base = saved_base[i];
+            c->ring_valid = saved_valid[i];
+            c->force_anc = saved_fa[i];
+            c->force_nex = saved_fn[i];
+        }
+    };
+    restore();
+    if (b->args_cap < args.size()) {
+        if (b->d_args) (void)hipFree(b->d_args);
+        b->d_args = nullptr;
+        b->args_cap = 0;
+        const int rc = dev_alloc(&b->d_args, args.size());
+        if (rc != PF_OK) return rc;
+        b->args_cap = args.size();
+    }
+    HIP_OK(hipStreamSynchronize(b->stream));   // earlier runs may still read d_args
+    HIP_OK(hipMemcpy(b->d_args, args.data(), args.size() * sizeof(StepArgs),
+                     hipMemcpyHostToDevice));
+    // graph mode: the launches are captured on a private stream (the legacy
+    // stream cannot be captured) and the graph is launched on the batch's
+    const hipStream_t run_stream = b->stream;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph) {
+        HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamDestroy(cap);
+            return PF_EHIP;
+        }
+        b->stream = cap;
+        for (pf_ctx *c : b->ctx) c->stream = cap;
+    }
+    int rc = PF_OK;
+    for (uint32_t t = 0; t < n_steps && rc == PF_OK; ++t) {
+        for (auto &r : rings[t]) {
+            rc = launch_ring(b->ctx[r.first], r.second);
+            if (rc != PF_OK) break;
+        }
+        uint32_t slot = 0;
+        for (auto &g : b->groups) {
+            if (rc != PF_OK) break;
+            const StepArgs *ga = b->d_args + (size_t)t * nb + slot;
+            uint32_t cnt = (uint32_t)g.members.size();
+            void *kargs[] = {&ga, &g.d_first, &cnt};
+            if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds, b->stream) !=
+                hipSuccess)
+                rc = PF_EHIP;
+            for (uint32_t i : g.members) {
+                pf_ctx *c = b->ctx[i];
+                const uint64_t k = c->step + 1;
+                uint64_t base;
+                plan_ring(c, k, false, &base);   // the table state the host pass assumed
+                advance(c, k);
+            }
+            slot += cnt;
+        }
+        for (uint32_t i : b->solo) {
+            if (rc != PF_OK) break;
+            rc = launch_step(b->ctx[i], d_frames[i] + (size_t)t * frame_stride[i]);
+        }
+    }
+    if (use_graph) {
+        const hipError_t e = hipStreamEndCapture(cap, &graph);
+        b->stream = run_stream;
+        for (pf_ctx *c : b->ctx) c->stream = run_stream;
+        if (rc == PF_OK && e != hipSuccess) rc = PF_EHIP;
+        if (rc == PF_OK) {
+            hipGraphExec_t exec = nullptr;
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess ||
+                hipGraphLaunch(exec, run_stream) != hipSuccess ||
+                hipStreamSynchronize(run_stream) != hipSuccess)
+                rc = PF_EHIP;
+            if (exec) (void)hipGraphExecDestroy(exec);
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        if (rc != PF_OK) (void)hipGetLastError();
+    }
+    return rc;
+}
+
+void pf_batch_destroy(pf_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto &g : b->groups)
+        if (g.d_first) (void)hipFree(g.d_first);
+    if (b->d_args) (void)hipFree(b->d_args);
+    delete b;
 }
 
 size_t pf_debug_size(const pf_ctx *c, int which) {
@@ -775,6 +1053,7 @@ int pf_debug_get(pf_ctx *c, int which, void *dst, size_t bytes) {
             float *tmp = nullptr;
             int rc = dev_alloc(&tmp, 5 * c->N);
             if (rc != PF_OK) return rc;
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
             hipLaunchKernelGGL(k_materialize, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0,
                                c->stream, cur_prop(c), cur_anc(c), tmp, (uint32_t)c->N,
                                c->cfg.n_per_pe);
@@ -818,6 +1097,7 @@ int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, ui
     if (c->g_cap) return PF_ESTATE;
     HIP_OK(hipStreamSynchronize(c->stream));
     HIP_OK(hipMemcpy(c->prop[c->cur], state, 5 * c->N * sizeof(float), hipMemcpyHostToDevice));
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_identity, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream,
                        c->anc[c->cur], (uint32_t)c->N, c->cfg.n_per_pe);
     HIP_OK(hipGetLastError());
@@ -872,6 +1152,7 @@ int pf_debug_resample_q(const uint32_t *q, uint32_t n_blocks, uint32_t n_p, cons
             hipMemcpy(dv, v, (size_t)n_blocks * 4, hipMemcpyHostToDevice) != hipSuccess)
             rc = PF_EHIP;
         if (rc == PF_OK) {
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
             if (n_p > 1024)
                 hipLaunchKernelGGL(k_resample_q<4>, dim3(n_blocks), dim3(B), 0, 0, dq, dv, da,
                                    n_p);
@@ -901,6 +1182,7 @@ int pf_debug_nex(const uint32_t *p, uint32_t M, uint32_t n_p, uint32_t mode, flo
     if (rc == PF_OK) {
         if (hipMemcpy(dp, p, M * 4, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
         if (rc == PF_OK) {
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
             hipLaunchKernelGGL(k_nex, dim3(1), dim3(256), 0, 0, dp, M, n_p, mode,
                                first_iteration, fixed_count(fixed_ratio, n_p),
                                fixed_count(initial_ratio, n_p), cutoff_ppm_of(eff_cutoff), dout);
@@ -925,6 +1207,7 @@ int pf_debug_ring(uint64_t seed, uint32_t f, uint32_t k, uint32_t M, uint32_t mo
     uint16_t *dt = nullptr;
     int rc = dev_alloc(&dt, (size_t)(f + 1) * M);
     if (rc != PF_OK) return rc;
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     hipLaunchKernelGGL(k_ring, dim3(1, f + 1), dim3(256), ring_lds_bytes(M, groups), 0, dt, k,
                        f + 1, M, groups, (uint32_t)seed, (uint32_t)(seed >> 32));
     uint16_t *h = (uint16_t *)malloc((size_t)M * 2);
@@ -949,6 +1232,7 @@ int pf_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t n, uint32
     if (rc == PF_OK) {
         if (hipMemcpy(dc, ctr, (size_t)16 * n, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
         if (rc == PF_OK) {
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
             hipLaunchKernelGGL(k_philox, dim3((n + 255) / 256), dim3(256), 0, 0, dc, key[0],
                                key[1], n, dout);
             if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||

@@ -347,16 +347,16 @@ enum LikKind { kLikGauss = 0, kLikPoint = 1, kLikPoisson = 2 };
 // slots s = t + q B, q < PPT (B = blockDim.x), so every global access of a
 // slot level is coalesced.
 template <int PPT, int HALF, int LIK>
-__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int P = 2 * HALF + 1;
     const uint32_t M = a.M, np = a.np, N = a.N;
-    const uint32_t f = blockIdx.x / M, m = blockIdx.x % M;
+    const uint32_t f = bid / M, m = bid % M;
     const uint32_t tid = threadIdx.x, B = blockDim.x;
     const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, nwaves = B / kWave;
     Lds L = carve(smem, np);
     uint16_t *recv = L.recv;
-    const uint32_t pe_base = blockIdx.x * np;   // (f M + m) N_p
+    const uint32_t pe_base = bid * np;   // (f M + m) N_p
     const DebugBufs *D = a.dbg;
     const int32_t *lin_in = D ? D->lin[a.lin_in] : nullptr;
     int32_t *lin_out = D ? D->lin[1 - a.lin_in] : nullptr;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     bool tile_on = false, tile_inside = false;
     constexpr bool POINT = LIK == kLikPoint;
     if (!POINT) {
-        const double *xh = a.rin[blockIdx.x].xhat;
+        const double *xh = a.rin[bid].xhat;
         const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
         // the tile pays for its 4096 loads only with a full workgroup of particles
         if (B >= 1024 && fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
@@ -423,7 +423,8 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         tv[i] = in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
     }
     float e[PPT][5];
-    const bool helpers = nwaves > 1;   // other waves draw wave 0's normals
+    // waves 1..PPT draw wave 0's normals (one of its slot levels each)
+    const bool helpers = nwaves > (uint32_t)PPT;
     if (helpers && tid >= kWave && tid < kWave * (PPT + 1)) {
         // wave 0's slot of lane j % 64 at level j / 64
         const uint32_t j = tid - kWave;
@@ -633,14 +634,14 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
         for (int c = 0; c < 5; ++c) r.xhat[c] = tot[1 + c] / tot[0];
         r.lstar = lstar;
         r.total_q = T;
-        a.rout[blockIdx.x] = r;
+        a.rout[bid] = r;
         if (m == 0) {
             a.nex_used[f] = p.nex;
             if (a.nex_rec) a.nex_rec[f] = p.nex;
         }
         if (trace) {
-            D->t_pred[blockIdx.x] = p.pred;
-            D->t_v[blockIdx.x] = V;
+            D->t_pred[bid] = p.pred;
+            D->t_v[bid] = V;
         }
     }
     if (a.mout) {
@@ -660,6 +661,30 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
             if (tid == 0) atomicExch(&a.arrive[f], 0u);
         }
     }
+}
+
+template <int PPT, int HALF, int LIK>
+__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+    step_body<PPT, HALF, LIK>(a, blockIdx.x);
+}
+
+// Several independent filter contexts in one launch: context i owns the
+// workgroups [first[i], first[i + 1]), one per PE, and its arguments are
+// args[i] (all contexts of a launch share PPT, the block size, the patch size
+// and the likelihood).  The work of a workgroup is exactly that of k_step.
+template <int PPT, int HALF, int LIK>
+__global__ __launch_bounds__(1024) void k_step_batch(const StepArgs *args, const uint32_t *first,
+                                                     uint32_t n) {
+    uint32_t lo = 0, hi = n;   // the context whose range holds this workgroup
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (first[mid] <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const StepArgs a = args[lo];
+    step_body<PPT, HALF, LIK>(a, blockIdx.x - first[lo]);
 }
 
 // Step 1 for kRingSteps iterations at once: Fisher-Yates (Durstenfeld,

@@ -11,12 +11,14 @@ from . import _native as nat
 
 CONFIG_KEYS = ("n_filters", "n_pe", "n_per_pe", "width", "height", "patch", "mode",
                "init_mode", "lik_mode", "fixed_ratio", "initial_ratio", "eff_cutoff",
-               "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed", "ring_groups")
+               "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed", "ring_groups",
+               "block_size")
 
 DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
                 mode=nat.PF_MODE_RNA, init_mode=nat.PF_INIT_TRACKING, lik_mode=nat.PF_LIK_PATCH,
                 fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
-                background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1, ring_groups=0)
+                background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1, ring_groups=0,
+                block_size=0)
 
 
 def _ptr(a: np.ndarray):
@@ -266,3 +268,46 @@ def philox(ctr, key) -> np.ndarray:
     nat.check(nat.lib().pf_debug_philox(_ptr(c), _ptr(k), c.shape[0], _ptr(out)),
               "pf_debug_philox")
     return out
+
+
+class Batch:
+    """Several Trackers advanced together (pf_batch_*): one launch per group
+    of contexts sharing a kernel variant, optionally one HIP graph per run."""
+
+    def __init__(self, trackers):
+        self.trackers = list(trackers)
+        arr = (ctypes.c_void_p * len(self.trackers))(*[t._h for t in self.trackers])
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().pf_batch_create(arr, len(self.trackers), ctypes.byref(h)),
+                  "pf_batch_create")
+        self._h = h
+
+    def run(self, frames, n_steps: int | None = None, graph: bool = False) -> None:
+        """frames[i]: the frames of tracker i (first axis = iteration)."""
+        if len(frames) != len(self.trackers):
+            raise ValueError("one frame stack per tracker")
+        n = min(f.shape[0] for f in frames) if n_steps is None else n_steps
+        ptrs, strides = [], []
+        for t, f in zip(self.trackers, frames):
+            if f.shape[0] < n:
+                raise ValueError("more steps than frames")
+            stride = int(np.prod(f.shape[1:]))
+            if stride != t.frame_numel():
+                raise ValueError(f"frames hold {stride} values each, expected {t.frame_numel()}")
+            ptrs.append(_dev_ptr(f, "frames").value)
+            strides.append(stride)
+        P = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        S = (ctypes.c_uint64 * len(strides))(*strides)
+        nat.check(nat.lib().pf_batch_run(self._h, P, S, n, 1 if graph else 0), "pf_batch_run")
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            nat.lib().pf_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
