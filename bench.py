@@ -192,6 +192,8 @@ def main():
                     choices=sorted(synth.WORKLOADS))
     ap.add_argument("--grad-frames", type=int, default=50,
                     help="frames of the fwd+bwd/fwd measurement (0: skip)")
+    ap.add_argument("--batch-frames", type=int, default=20,
+                    help="frames of the 64-sequence batched measurement (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -251,6 +253,9 @@ def main():
         gl = grad_leg(args.grad_workload, args.grad_frames, args.seed)
         line["fwd_bwd_over_fwd"] = gl["fwd_bwd_over_fwd"]
         line["grad"] = gl
+    if args.batch_frames:
+        from paper_1310_4624_amd.experiments import batch
+        line["batch"] = batch(frames=args.batch_frames)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_leg(args.workload, args.seed, args.cpu_budget, g["seq"])
     print(json.dumps(line), flush=True)

@@ -110,9 +110,76 @@ def scaling(mode: str, n_pe: int, total: int = 1 << 20, steps: int = 30, warmup:
                 us_per_step=float(ms[~ring].mean() * 1e3), n_ex=int(est["n_ex"][0]))
 
 
+def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000) -> dict:
+    """The batched workload: n_seq independent sequences of uneven size run
+    (a) one after another, one launch per sequence and iteration, (b) as one
+    batch (one launch per kernel variant and iteration), (c) the batch as one
+    HIP graph (captured and instantiated inside the timed region), (d) (b) and
+    (c) with the workgroup sizes chosen by the autotuner.
+    Throughput = total particle-steps / time between two events."""
+    import torch
+    from . import autotune
+    from .tracker import Batch
+    seqs = synth.batch_sequences(seed=seed, n_seq=n_seq, frames=frames)
+    dev = [torch.from_numpy(fr).cuda() for _, _, fr in seqs]
+    total = sum(c["n_filters"] * c["n_pe"] * c["n_per_pe"] for c, _, _ in seqs) * frames
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def make(block_sizes=None):
+        return [Tracker(dict(c, block_size=(block_sizes[i] if block_sizes else 0)), t)
+                for i, (c, t, _) in enumerate(seqs)]
+
+    out = {"n_seq": n_seq, "frames": frames, "particle_steps": total}
+    # warm-up: load every kernel variant once
+    trs = make()
+    Batch(trs).run([d[:1] for d in dev])
+    for t in trs:
+        t.close()
+    trs = make()
+    ms = timed(lambda: [t.run(d) for t, d in zip(trs, dev)])
+    ref = [t.estimate()["x_global"] for t in trs]
+    for t in trs:
+        t.close()
+    out["sequential_ms"] = ms
+    for name, graph in (("batched_ms", False), ("batched_graph_ms", True)):
+        trs = make()
+        b = Batch(trs)
+        out[name] = timed(lambda: b.run(dev, graph=graph))
+        out[name.replace("_ms", "_equal")] = all(
+            np.array_equal(t.estimate()["x_global"], r) for t, r in zip(trs, ref))
+        b.close()
+        for t in trs:
+            t.close()
+    if tune:
+        blocks = [autotune.tune(c, t, d, steps=min(6, frames - 2)) for (c, t, _), d in zip(seqs, dev)]
+        for name, graph in (("batched_tuned_ms", False), ("batched_graph_tuned_ms", True)):
+            trs = make(blocks)
+            b = Batch(trs)
+            out[name] = timed(lambda: b.run(dev, graph=graph))
+            b.close()
+            for t in trs:
+                t.close()
+        out["tuned_block_sizes"] = blocks
+        out["default_block_sizes"] = [min(1024, (c["n_per_pe"] + 63) // 64 * 64) for c, _, _ in seqs]
+    for k in list(out):
+        if k.endswith("_ms"):
+            out[k.replace("_ms", "_particle_steps_per_s")] = total / (out[k] / 1e3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling"])
+    ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling",
+                                     "batch"])
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
     ap.add_argument("--ring-groups", type=int, default=0)
     ap.add_argument("--modes", default="arna,rna10,rna50,rna0")
@@ -123,6 +190,9 @@ def main():
     ap.add_argument("--curves", action="store_true", help="include the per-step curves")
     args = ap.parse_args()
     out = []
+    if args.what == "batch":
+        print(json.dumps(batch(frames=args.steps or 20)), flush=True)
+        return
     if args.what == "curves":
         for n_pe in (24, 96, 192, 384):
             for s in range(args.seeds):

@@ -207,6 +207,54 @@ def filter_config(workload: str, **overrides) -> dict:
     return d
 
 
+# ---------------------------------------------------------- batched sequences
+def render_windowed(truth_k, width, height, psf_sigma, background, noise_sigma, rng, reach=8):
+    """Like render(), with each spot evaluated only within `reach` px of its
+    centre (its profile is below 1e-6 of the peak beyond 8 px at s = 1.5)."""
+    img = np.full((height, width), float(background))
+    for s in range(truth_k.shape[0]):
+        x, y, _, _, I0 = truth_k[s]
+        u0, u1 = max(int(np.floor(x)) - reach, 0), min(int(np.floor(x)) + reach + 1, width)
+        v0, v1 = max(int(np.floor(y)) - reach, 0), min(int(np.floor(y)) + reach + 1, height)
+        if u0 >= u1 or v0 >= v1:
+            continue
+        ys, xs = np.mgrid[v0:v1, u0:u1].astype(np.float64)
+        img[v0:v1, u0:u1] += I0 * np.exp(-((xs - x) ** 2 + (ys - y) ** 2) / (2 * psf_sigma ** 2))
+    img += noise_sigma * rng.standard_normal((height, width))
+    return img.astype(np.float32)
+
+
+def batch_sequences(seed: int = 2000, n_seq: int = 64, frames: int = 50):
+    """Independent tracking problems of uneven size for the batched launch:
+    frames of 256^2, 512^2 or 1024^2, 1-3 spots of SNR 2-8 (one filter per
+    spot), 2^14..2^20 particles (log-uniform) over 16..256 PEs (log-uniform);
+    N_p = N / (F M) is kept within 64..4096 (the LDS bound of one PE) by
+    moving M.  Returns [(cfg, truth [F][5] float32, frames [K][H][W])]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_seq):
+        side = int(rng.choice([256, 512, 1024]))
+        F = int(rng.integers(1, 4))
+        N = int(round(2 ** rng.uniform(14, 20)))
+        M = int(round(2 ** rng.uniform(4, 8)))
+        n_p = max(64, N // (F * M))
+        while n_p > 4096:
+            M *= 2
+            n_p = max(64, N // (F * M))
+        snr = rng.uniform(2.0, 8.0, F)
+        cfg = dict(n_filters=F, n_pe=M, n_per_pe=n_p, width=side, height=side, patch=9,
+                   mode=MODE_ARNA, init_mode=INIT_TRACKING, lik_mode=LIK_PATCH,
+                   fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
+                   background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1 + i)
+        lo, hi = 0.3 * side, 0.7 * side
+        truth = trajectories(rng, F, frames, side, side, list(2.0 * snr), "ncv", (0.3, 1.0),
+                             (lo, hi), 16.0, 12.0, q=0.001)
+        fr = np.stack([render_windowed(truth[k], side, side, 1.5, 5.0, 2.0, rng)
+                       for k in range(1, frames + 1)])
+        out.append((cfg, truth[0].astype(np.float32), fr))
+    return out
+
+
 # ----------------------------------------------------------------- small cases
 def point_sequence(seed, n_filters, n_frames, q=0.5, r=1.0, start=(64.0, 64.0), I0=10.0):
     """Linear-Gaussian case: NCV truth (no reflection) and noisy position
