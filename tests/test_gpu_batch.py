@@ -105,3 +105,17 @@ def test_batch_rejects_bad_input():
     b.run([fr])
     b.close()
     t.close()
+
+
+def test_autotuner_and_batched_workload():
+    """The autotuner returns one of its candidates; a small instance of the
+    batched workload runs in every mode with the separate runs' results."""
+    from paper_1310_4624_amd import autotune
+    from paper_1310_4624_amd.experiments import batch
+    seqs = synth.batch_sequences(seed=7, n_seq=3, frames=8)
+    c, t, fr = seqs[0]
+    b = autotune.tune(c, t, torch.from_numpy(fr).cuda(), steps=4)
+    assert b in autotune.candidates(c["n_per_pe"])
+    out = batch(frames=6, n_seq=4, seed=7)
+    assert out["batched_equal"] and out["batched_graph_equal"]
+    assert len(out["tuned_block_sizes"]) == 4
