@@ -1104,7 +1104,17 @@ int pf_debug_set_state(pf_ctx *c, const float *state, const double *log_mass, ui
     HIP_OK(hipStreamSynchronize(c->stream));
     pf_pe_record *rec = (pf_pe_record *)calloc(c->FM, sizeof(pf_pe_record));
     if (!rec) return PF_ENOMEM;
-    for (uint64_t i = 0; i < c->FM; ++i) rec[i].log_mass = log_mass ? log_mass[i] : 0.0;
+    // x^m of the loaded state: the mean of the PE's particles (it places the
+    // next iteration's image tile)
+    const uint32_t np = c->cfg.n_per_pe;
+    for (uint64_t i = 0; i < c->FM; ++i) {
+        rec[i].log_mass = log_mass ? log_mass[i] : 0.0;
+        for (int d = 0; d < 5; ++d) {
+            double acc = 0.0;
+            for (uint32_t j = 0; j < np; ++j) acc += (double)state[(size_t)d * c->N + i * np + j];
+            rec[i].xhat[d] = acc / np;
+        }
+    }
     const hipError_t e =
         hipMemcpy(c->rec[c->cur], rec, sizeof(pf_pe_record) * c->FM, hipMemcpyHostToDevice);
     free(rec);

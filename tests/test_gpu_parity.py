@@ -164,6 +164,21 @@ def seeded_case(name):
         truth = np.array([[[30.3, 40.7, 0, 0, 12.0], [70.6, 20.2, 0, 0, 9.0]]])
         frame = synth.render(truth[0], 96, 80, 1.5, 5.0, 2.0, rng)
         centre = truth[0, :, :2]
+    elif name in ("full_tracking_4x64x4096", "full_infoshare_256x4096"):
+        # the two 2^20 workloads in the launch configuration bench.py times;
+        # the information-sharing case with spread PEs (most patches read the
+        # frame, not the tile)
+        wl = ("arna_tracking_512_4x64x4096" if name.startswith("full_tracking")
+              else "arna_infoshare_512_256x4096")
+        cfg = synth.filter_config(wl, seed=SEED + 7)
+        seq = synth.make_sequence(wl, seed=1004, frames=3)
+        frame = seq.frames[2]
+        centre = seq.truth[3, :, :2]
+        F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
+        spread = 1.5 if name.startswith("full_tracking") else 40.0
+        state = synth.random_state(rng, F, M, n_p, cfg["width"], cfg["height"], spread=spread,
+                                   centre=centre, I0=10.0)
+        return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (F, M))
     elif name == "point_rna_3x5x77":
         cfg = dict(n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, patch=9,
                    mode=0, init_mode=0, lik_mode=1, fixed_ratio=0.5, initial_ratio=0.1,
@@ -200,7 +215,8 @@ def run_one_step(cfg, frame, state, logmass, k_done):
 
 @pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
                                   "poisson_arna_1x4x1000", "arna_2x2100x4", "arna_groups_2x24x300",
-                                  "point_rna_3x5x77"])
+                                  "point_rna_3x5x77", "full_tracking_4x64x4096",
+                                  "full_infoshare_256x4096"])
 @pytest.mark.parametrize("k_done", [0, 7])
 def test_one_step_parity(name, k_done):
     cfg, frame, state, logmass = seeded_case(name)
