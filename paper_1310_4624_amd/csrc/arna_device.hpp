@@ -117,7 +117,7 @@ struct Lik {
 //   l = (I sum g (z - B) - I^2 / 2 sum g^2) / sigma_n^2,
 // with the separable profile g(u, v) = gx(u) gy(v).  Pixels outside the image
 // are skipped (their weights are zero).  The patch position is decided first
-// (patch_origin); the sums then read the pixels from one of three sources.
+// (patch_origin); the sums then read the pixels from the LDS tile or the frame.
 template <int HALF>
 __device__ __forceinline__ bool patch_origin(float x, float y, int W, int H, int &u0, int &v0) {
     const float cxf = floorf(x + 0.5f);
@@ -132,12 +132,6 @@ __device__ __forceinline__ bool patch_origin(float x, float y, int W, int H, int
 
 enum PixelSource { kFromTile = 0, kFromImage = 1, kFromImageBorder = 2, kFromTileInside = 3 };
 
-// SRC = kFromTile: `pix` points at (z - B) of the patch's first pixel in an
-//   LDS tile of row pitch `pitch`, already zero outside the image;
-// SRC = kFromTileInside: the same, for a tile that lies inside the image;
-// SRC = kFromImage: `pix` points at the first pixel in the frame, the whole
-//   patch lies inside the image (row pitch = W);
-// SRC = kFromImageBorder: `pix` is the frame; every read is clamped and masked.
 // The P profile values exp(-(u0 + j - x)^2 c), j = 0..2 HALF, by a recurrence
 // outward from the centre pixel u0 + HALF (|d| <= 1/2): with d_j = u0 + j - x,
 //   g_{j+1} = g_j r_j,  r_j = exp(-(2 d_j + 1) c),  r_{j+1} = r_j exp(-2 c),
@@ -159,6 +153,7 @@ __device__ __forceinline__ void profile(float d_centre, float c, float k2, float
 
 // SRC = kFromTile: `pix` points at (z - B) of the patch's first pixel in an
 //   LDS tile of row pitch `pitch`, already zero outside the image;
+// SRC = kFromTileInside: the same, for a tile that lies inside the image;
 // SRC = kFromImage: `pix` points at the first pixel in the frame, the whole
 //   patch lies inside the image (row pitch = W);
 // SRC = kFromImageBorder: `pix` is the frame; every read is clamped and masked.
@@ -283,16 +278,6 @@ __device__ __forceinline__ float patch_loglik_poisson(const float s[5], int u0, 
     return acc;
 }
 
-// Patch likelihood straight from the frame (no LDS tile).
-template <int HALF>
-__device__ __forceinline__ float loglik_patch(const float s[5], const Lik &L) {
-    int u0, v0;
-    if (!patch_origin<HALF>(s[0], s[1], L.W, L.H, u0, v0)) return 0.0f;
-    constexpr int P = 2 * HALF + 1;
-    if (u0 >= 0 && v0 >= 0 && u0 + P <= L.W && v0 + P <= L.H)
-        return patch_loglik<HALF, kFromImage>(s, u0, v0, L.img + (size_t)v0 * L.W + u0, 0, L);
-    return patch_loglik<HALF, kFromImageBorder>(s, u0, v0, L.img, 0, L);
-}
 
 // Patch log-likelihood and its partial derivatives for the adjoint step:
 // g = (dl/dx, dl/dy, dl/dI, dl/dsigma) at the frozen patch origin (u0, v0)
@@ -411,18 +396,6 @@ __device__ __forceinline__ float wave_max_f32(float v) {
     });
     return __uint_as_float(lane63(r));
 }
-__device__ __forceinline__ int wave_min_i32(int v) {
-    const uint32_t r = wave_scan_bits((uint32_t)v, 0x7FFFFFFFu, [](uint32_t a, uint32_t b) {
-        return (uint32_t)min((int)a, (int)b);
-    });
-    return (int)lane63(r);
-}
-__device__ __forceinline__ int wave_max_i32(int v) {
-    const uint32_t r = wave_scan_bits((uint32_t)v, 0x80000000u, [](uint32_t a, uint32_t b) {
-        return (uint32_t)max((int)a, (int)b);
-    });
-    return (int)lane63(r);
-}
 // Sum of a double over the wave (every lane gets it), in a fixed order.
 __device__ __forceinline__ double wave_total_f64(double v) {
 #define ARNA_DPP_F64(CTRL, ROWS)                                                      \
@@ -444,12 +417,6 @@ __device__ __forceinline__ double wave_total_f64(double v) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// ---------------------------------------------------------------- reductions
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -466,18 +433,6 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Block-wide reductions; `scratch` holds at least 8 bytes per wave.  Every
-// thread of the block must call them; all threads get the result.
-__device__ __forceinline__ float block_max(float v, double *scratch) {
-    v = wave_max(v);
-    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) scratch[w] = (double)v;
-    __syncthreads();
-    float r = (float)scratch[0];
-    for (int i = 1; i < nw; ++i) r = fmaxf(r, (float)scratch[i]);
-    return r;
-}
 __device__ __forceinline__ double block_max_d(double v, double *scratch) {
     v = wave_max_d(v);
     const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
@@ -525,43 +480,6 @@ __device__ __forceinline__ void block_sum_u64(uint64_t (&v)[2], uint64_t *scratc
     v[1] = b;
 }
 
-// Inclusive prefix sum of c[0..n) in LDS (uint32, exact).  Thread t scans the
-// contiguous chunk [t * per, (t + 1) * per); the chunk totals are scanned
-// across each wave with shuffles and across waves through `wtot`
-// (>= blockDim.x / 64 entries).  Returns the grand total to every thread.
-__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t *c, int n, int per,
-                                                         uint32_t *wtot) {
-    const int t = threadIdx.x;
-    const int lane = t & (kWave - 1), w = t / kWave, nw = blockDim.x / kWave;
-    const int b = t * per;
-    uint32_t run = 0;
-    for (int i = 0; i < per; ++i)
-        if (b + i < n) run += c[b + i];
-    // inclusive scan of the chunk totals within the wave
-    uint32_t incl = run;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
-    }
-    __syncthreads();
-    if (lane == kWave - 1) wtot[w] = incl;
-    __syncthreads();
-    uint32_t base = 0, total = 0;
-    for (int i = 0; i < nw; ++i) {
-        const uint32_t x = wtot[i];
-        if (i < w) base += x;
-        total += x;
-    }
-    uint32_t acc = base + incl - run;
-    for (int i = 0; i < per; ++i)
-        if (b + i < n) {
-            acc += c[b + i];
-            c[b + i] = acc;
-        }
-    __syncthreads();
-    return total;
-}
 
 // Wave-wide inclusive prefix maximum of unsigned values (identity 0), and the
 // exclusive one (the inclusive value of the previous lane, 0 for lane 0).

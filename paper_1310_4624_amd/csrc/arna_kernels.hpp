@@ -558,7 +558,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
     if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
-    __syncthreads();   // barrier 4: wave maxima (tile reads done)
+    __syncthreads();   // barrier 2: wave maxima (tile reads done)
     float lstar = L.wmax[0];
     for (uint32_t w = 1; w < nwaves; ++w) lstar = fmaxf(lstar, L.wmax[w]);
 
@@ -598,11 +598,11 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
 #pragma unroll
         for (int c = 0; c < 6; ++c) L.wsum[wave * 6 + c] = sums[c];
     }
-    __syncthreads();   // barrier 5: wave totals, marks cleared
+    __syncthreads();   // barrier 3: wave totals, marks cleared
     const uint32_t T = scan_finish<PPT>(cinc, L.wq);
     const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
     mark_offspring<PPT>(Qv, cinc, np, T, V, mark);
-    __syncthreads();   // barrier 6: marks complete
+    __syncthreads();   // barrier 4: marks complete
 
     // ---- phase 4 (step 7): ancestors as prefix maxima of the marks; only the
     // indices are stored (the propagated particles went out in phase 1).
