@@ -781,6 +781,8 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
             a.force_nex = c->g_nex + (size_t)i * F;   // N_ex as the forward iteration used it
             AdjArgs g;
             g.xprop = c->g_prop + (size_t)i * 5 * N;
+            g.xprev = c->g_prop + (size_t)(i - 1) * 5 * N;
+            g.ancprev = c->g_anc + (size_t)(i - 1) * N;
             g.anck = c->g_anc + (size_t)i * N;
             g.rbar_in = (i == K) ? nullptr : c->g_bar[i & 1];
             g.rbar_out = c->g_bar[(i - 1) & 1];

@@ -23,7 +23,8 @@
 //   to the velocity adjoint), written to the slot the input came from (own
 //   slot, or pred's sent slot: a bijection, no conflicts);
 //   dJ/dsigma += ubar_j dl_j/dsigma;  dJ/dq += xbar_j . n_j / (2 q), n_j the
-//   process noise of slot j (proportional to sqrt q).
+//   process noise of slot j (proportional to sqrt q), read back from the tape
+//   as x_j - F x_in(j).
 #pragma once
 
 #include "arna_kernels.hpp"
@@ -32,6 +33,10 @@ namespace {
 
 struct AdjArgs {
     const float *xprop;       // [5][N] propagated particles of step k
+    const float *xprev;       // [5][N] propagated particles of step k - 1 (the tape's start
+                              // state at the first recorded step)
+    const uint16_t *ancprev;  // [N] ancestors of step k - 1: slot s of PE p held
+                              // xprev[p N_p + ancprev[p N_p + s]] after step k - 1
     const uint16_t *anck;     // [N] ancestors of step k (sorted within each PE)
     const float *rbar_in;     // [5][N] adjoint of the resampled slots of step k; NULL at k = K
     float *rbar_out;          // [5][N] adjoint of the resampled slots of step k - 1
@@ -158,6 +163,14 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
         float x[5], xb[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 5; ++c) x[c] = g.xprop[c * N + pe_base + j];
+        // the input of slot j (own slot, or pred's sent slot): its process
+        // noise is n = x - F x_in; loaded now, used after the likelihood
+        const uint32_t r = recv[j];
+        const uint32_t src_base = (r != 0xFFFFu) ? pred_base : pe_base;
+        const uint32_t src = src_base + g.ancprev[src_base + ((r != 0xFFFFu) ? r : j)];
+        float xin[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xin[c] = g.xprev[c * N + src];
         float gl[4] = {0, 0, 0, 0}, ell = 0.f;
         int u0, v0;
         if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
@@ -173,7 +186,6 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
             for (uint32_t t = rs[j]; t < re[j]; ++t)
 #pragma unroll
                 for (int c = 0; c < 5; ++c) xb[c] += rb[c * np + t];
-        const uint32_t r = recv[j];
         const float lam = (r != 0xFFFFu) ? p.lam_pred : p.lam_own;
         const float ub = (logw == -INFINITY) ? 0.f : lbar * __expf((lam + ell) - logw);
         xb[0] += ub * gl[0];
@@ -181,11 +193,9 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
         xb[4] += ub * gl[2];
         sums[(r != 0xFFFFu) ? 1 : 0] += (double)ub;
         sums[2] += (double)(ub * gl[3]);
-        // process noise of this slot, sqrt(q) times a fixed combination of normals
-        float e[5];
-        five_normals(philox(m * np + j, a.k, f, kTagProp << 24, a.key0, a.key1), e);
-        const float n0 = a.dyn.a * e[0], n2 = a.dyn.b * e[0] + a.dyn.c * e[1];
-        const float n1 = a.dyn.a * e[2], n3 = a.dyn.b * e[2] + a.dyn.c * e[3];
+        // process noise of this slot (proportional to sqrt q): x - F x_in
+        const float n0 = x[0] - (xin[0] + xin[2]), n2 = x[2] - xin[2];
+        const float n1 = x[1] - (xin[1] + xin[3]), n3 = x[3] - xin[3];
         sums[3] += (double)(g.inv_2q * (xb[0] * n0 + xb[2] * n2 + xb[1] * n1 + xb[3] * n3));
         sums[4] += (double)xb[4];
         // adjoint of the input (F^T), to the slot the input came from
