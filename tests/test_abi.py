@@ -97,6 +97,12 @@ def _init(L, **kw):
     (dict(q=-1.0), nat.PF_EINVAL),
     (dict(width=0), nat.PF_EINVAL),
     (dict(struct_size=12), nat.PF_EINVAL),
+    (dict(lik_mode=3), nat.PF_EINVAL),
+    (dict(lik_mode=nat.PF_LIK_POISSON, background=0.0), nat.PF_EINVAL),
+    (dict(ring_groups=257), nat.PF_EINVAL),
+    (dict(block_size=100), nat.PF_EINVAL),             # not a multiple of 64
+    (dict(block_size=2048), nat.PF_EINVAL),            # above 1024
+    (dict(n_per_pe=4096, block_size=512), nat.PF_EINVAL),   # 4 slots per thread do not cover N_p
 ])
 def test_init_rejects_bad_config_on_host(L, bad, code):
     assert _init(L, **bad) == code
@@ -110,6 +116,14 @@ def test_null_arguments_rejected(L):
     assert L.pf_debug_get(None, 0, None, 0) == nat.PF_EINVAL
     assert L.pf_debug_size(None, 0) == 0
     L.pf_destroy(None)
+    assert L.pf_grad_begin(None, 1) == nat.PF_EINVAL
+    assert L.pf_grad_end(None, None, 0, None) == nat.PF_EINVAL
+    assert L.pf_grad_value(None, None) == nat.PF_EINVAL
+    assert L.pf_debug_force_next(None, None, None) == nat.PF_EINVAL
+    out = ctypes.c_void_p()
+    assert L.pf_batch_create(None, 0, ctypes.byref(out)) == nat.PF_EINVAL
+    assert L.pf_batch_run(None, None, None, 1, 0) == nat.PF_EINVAL
+    L.pf_batch_destroy(None)
 
 
 def test_debug_resample_rejects_bad_offsets_on_host(L):
