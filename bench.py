@@ -52,9 +52,10 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, ring_groups: int = 0):
-    """HBM bytes per k_step launch from the committed counter summary, or None
-    when the kernel sources changed since it was taken."""
+def measured_counters(workload: str, ring_groups: int = 0):
+    """Counter summary of k_step (HBM bytes and VALU instructions per launch)
+    from profiles/k_step_traffic.json, or None when the kernel sources changed
+    since the counters were taken or the workload differs."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -63,7 +64,12 @@ def measured_traffic(workload: str, ring_groups: int = 0):
     if (t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload
             or t.get("ring_groups", 0) != ring_groups):
         return None
-    return t.get("bytes_per_launch")
+    return t
+
+
+# VALU issue: 256 CUs x 4 SIMDs at 2.4 GHz, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes wide)
+VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 
 
 def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int, ring_groups: int = 0):
@@ -221,6 +227,7 @@ def main():
     # average launch duration over the timed region (one launch per step; the
     # region's events bracket the whole pf_run, so gaps between launches count)
     achieved = bytes_launch / (ms / 1e3) / 1e9
+    counters = measured_counters(args.workload, args.ring_groups)
     line = {
         "metric": METRIC,
         "value": value,
@@ -242,10 +249,15 @@ def main():
                    "parallelism": "one PE per workgroup, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, args.ring_groups),
+                     "traffic": (counters or {}).get("bytes_per_launch"),
                      "kernel": "k_step", "kernel_ms": ms,
                      "event_ms_per_launch": g["step_kernel_ms"],
                      "bytes_per_launch": bytes_launch, "kernel_sha": kernel_sha()},
+        "valu": None if not counters or "valu_insts" not in counters else {
+            "insts_per_launch": counters["valu_insts"],
+            "issue_ms": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3,
+            "busy_frac": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3 / ms,
+            "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S},
         "final_pe_eff": g["pe_eff"],
         "final_n_ex": g["n_ex"],
     }
