@@ -40,12 +40,22 @@ enum {
     PF_EHIP = -3,          /* a HIP runtime call failed */
     PF_ENUMERIC = -4,      /* a log-weight was NaN (e.g. a NaN pixel); sticky */
     PF_ESTATE = -5,        /* call out of order (e.g. pf_exchange twice) */
-    PF_EUNSUPPORTED = -6   /* size beyond the limits below */
+    PF_EUNSUPPORTED = -6,  /* size beyond the limits below */
+    PF_ETIMEOUT = -7       /* workgroups of a multi-iteration launch waited for each
+                              other longer than 2 s (results undefined); sticky */
 };
 
 enum { PF_MODE_RNA = 0, PF_MODE_ARNA = 1 };
 enum { PF_INIT_TRACKING = 0, PF_INIT_INFOSHARE = 1 };
 enum { PF_LIK_PATCH = 0, PF_LIK_POINT = 1, PF_LIK_POISSON = 2 };
+/* How pf_run launches its iterations (pf_config.launch). */
+enum { PF_LAUNCH_AUTO = 0,        /* multi-iteration launches for contexts of at most 64
+                                     PEs in all (where they are faster), else one launch
+                                     per iteration */
+       PF_LAUNCH_STEPWISE = 1,    /* one launch per iteration */
+       PF_LAUNCH_PERSISTENT = 2   /* multi-iteration launches whatever the size; pf_init
+                                     fails with PF_EUNSUPPORTED when the context cannot use
+                                     them */ };
 
 /* Debug flags (pf_config.debug). */
 enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the last step */
@@ -94,6 +104,19 @@ typedef struct {
                                  * multiple of 64 in 64..1024 with block_size * P >= N_p
                                  * for P = 1, 2 or 4 slots per thread (the smallest such P
                                  * is used) -- the knob of the autotuner */
+    uint32_t launch;            /* PF_LAUNCH_*.  A multi-iteration launch runs up to 64
+                                 * iterations with every PE's workgroup resident on its
+                                 * compute unit: its resampled particles stay in registers,
+                                 * only received slots are read back, and the PEs of a filter
+                                 * meet at a barrier between iterations instead of a launch
+                                 * boundary.  It needs a 9 x 9 patch or point data, no debug
+                                 * flag, M < 2048, and F M workgroups resident at once
+                                 * (cooperative launch; e.g. F M <= 256 at N_p = 4096 on
+                                 * MI355X).  Results are bitwise those of one launch per
+                                 * iteration.  Iterations that record a gradient tape or
+                                 * replay forced choices always run one launch each.  The
+                                 * barrier costs less than a launch boundary only for small
+                                 * contexts, hence the AUTO rule. */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;
@@ -135,12 +158,17 @@ int pf_step(pf_ctx *c, const float *d_frame);
  * (stride in floats).  Same semantics as n_steps calls of pf_step. */
 int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride);
 
-/* pf_run that also times every iteration with a pair of HIP events recorded
- * on the context's stream around its launches, then synchronizes the stream.
- * host_ms_out (host float [n_steps]) receives each iteration's duration in
- * milliseconds (the ring table build of every 64th iteration included). */
+/* pf_run that also times every launch with a pair of HIP events recorded on
+ * the context's stream around it, then synchronizes the stream.  host_ms_out
+ * (host float [n_steps]) receives each iteration's duration in milliseconds:
+ * that of its launch divided by the iterations the launch ran (the ring table
+ * build of every 64th iteration included). */
 int pf_run_timed(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
                  float *host_ms_out);
+
+/* *host_multi = 1 if pf_run may use multi-iteration launches for this context
+ * (see pf_config.launch), else 0. */
+int pf_run_info(const pf_ctx *c, uint32_t *host_multi);
 
 /* Steps 1-3 of the next iteration alone (Alg. 3; Sec. III-A/C, IV-A/B):
  * ring, exchange ratio and particle exchange.  If d_src_map (device int64 [N])

@@ -13,9 +13,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libarna.so")
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENUMERIC, PF_ESTATE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PF_ETIMEOUT = -7
 PF_MODE_RNA, PF_MODE_ARNA = 0, 1
 PF_INIT_TRACKING, PF_INIT_INFOSHARE = 0, 1
 PF_LIK_PATCH, PF_LIK_POINT, PF_LIK_POISSON = 0, 1, 2
+PF_LAUNCH_AUTO, PF_LAUNCH_STEPWISE, PF_LAUNCH_PERSISTENT = 0, 1, 2
 PF_DEBUG_TRACE, PF_DEBUG_LINEAGE = 1, 2
 PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 4096, 15
 
@@ -42,6 +44,7 @@ class pf_config(ctypes.Structure):
         ("debug", ctypes.c_uint32),
         ("ring_groups", ctypes.c_uint32),
         ("block_size", ctypes.c_uint32),
+        ("launch", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]
@@ -80,6 +83,7 @@ SIGNATURES = {
     "pf_run": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64]),
     "pf_run_timed": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64,
                                     ctypes.POINTER(ctypes.c_float)]),
+    "pf_run_info": (ctypes.c_int, [_P, _U32P]),
     "pf_exchange": (ctypes.c_int, [_P, _P]),
     "pf_estimate": (ctypes.c_int, [_P, ctypes.POINTER(pf_estimate_t)]),
     "pf_destroy": (None, [_P]),

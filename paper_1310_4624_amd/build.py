@@ -4,14 +4,23 @@ from __future__ import annotations
 import os
 import shutil
 import subprocess
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "arna.hip")
-DEPS = [SRC, os.path.join(PKG, "csrc", "arna_device.hpp"), os.path.join(PKG, "csrc", "arna_kernels.hpp"),
-        os.path.join(PKG, "csrc", "arna_adjoint.hpp"), os.path.join(ROOT, "include", "arna.h")]
+# k_run is compiled on its own, with machine-level loop-invariant code motion
+# off: hoisting constants out of its iteration loop holds them in registers
+# across the loop and spills
+SRC_RUN = os.path.join(PKG, "csrc", "arna_run.hip")
+DEPS = [SRC, SRC_RUN, os.path.join(PKG, "csrc", "arna_device.hpp"),
+        os.path.join(PKG, "csrc", "arna_kernels.hpp"), os.path.join(PKG, "csrc", "arna_adjoint.hpp"),
+        os.path.join(ROOT, "include", "arna.h")]
 LIB = os.path.join(PKG, "libarna.so")
 ARCH = "gfx950"
+# packed FP32 instructions stay off (they are not used by this code)
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+RUN_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 
 def hipcc() -> str:
@@ -21,20 +30,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str) -> list:
-    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-            # packed FP32 instructions stay off (they are not used by this code)
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"), "-o", out, SRC]
+def commands(out: str, objdir: str) -> list:
+    """hipcc command lines: one object per translation unit, then the link."""
+    inc = ["-I", os.path.join(ROOT, "include")]
+    o_main = os.path.join(objdir, "arna.o")
+    o_run = os.path.join(objdir, "arna_run.o")
+    arch = f"--offload-arch={ARCH}"
+    return [[hipcc(), arch, *FLAGS, *inc, "-c", "-o", o_main, SRC],
+            [hipcc(), arch, *FLAGS, *RUN_FLAGS, *inc, "-c", "-o", o_run, SRC_RUN],
+            [hipcc(), arch, "-fPIC", "-shared", "-o", out, o_main, o_run]]
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    res = subprocess.run(command(tmp), capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    if verbose:
-        print(res.stderr)
+    with tempfile.TemporaryDirectory() as objdir:
+        cmds = commands(tmp, objdir)
+        # the two translation units compile in parallel
+        procs = [subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+                 for c in cmds[:2]]
+        outs = [p.communicate() for p in procs]
+        for p, (o, e) in zip(procs, outs):
+            if p.returncode != 0:
+                raise RuntimeError("hipcc failed:\n" + o + e)
+            if verbose:
+                print(e)
+        res = subprocess.run(cmds[2], capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + res.stdout + res.stderr)
     os.replace(tmp, LIB)
     return LIB
 

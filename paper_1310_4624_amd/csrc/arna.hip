@@ -76,6 +76,12 @@ struct pf_ctx {
     // master records (used when M >= kMasterMinPE), ping-pong like the records
     MasterRec *mrec[2];
     uint32_t *arrive;
+    // multi-iteration launches (k_run): kernel, or NULL when the context
+    // cannot keep all its workgroups resident; barrier counters and wait limit
+    void *run_fn;
+    unsigned long long *bar;
+    unsigned long long bar_timeout;
+    StepArgs *run_args;            // [kRunMaxSteps] arguments of a k_run launch
     EstDev *est;
     DebugBufs *d_dbg;              // device copy of the debug-buffer table, or NULL
     // trace buffers
@@ -214,6 +220,10 @@ void *pick_batch_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
     return batch_kernel_ppt<4, kLikGauss>(ppt);
 }
 
+void *pick_run_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
+    return arna_run_kernel(ppt, half, lik_mode);
+}
+
 template <int PPT, int HALF>
 void *adj_kernel() {
     return reinterpret_cast<void *>(&k_adjoint<PPT, HALF>);
@@ -249,6 +259,7 @@ int validate(const pf_config *c) {
     if (c->n_pe > PF_MAX_PE || c->n_per_pe > PF_MAX_PER_PE) return PF_EUNSUPPORTED;
     if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
     if (c->ring_groups > 256) return PF_EINVAL;
+    if (c->launch > PF_LAUNCH_PERSISTENT) return PF_EINVAL;
     if (c->block_size) {
         if (c->block_size % 64 || c->block_size > 1024) return PF_EINVAL;
         if ((uint64_t)c->block_size * 4 < c->n_per_pe) return PF_EINVAL;
@@ -279,7 +290,7 @@ void free_all(pf_ctx *c) {
                     c->lin[0], c->lin[1],
                     c->ring_tab, c->err, c->nex_used, c->est, c->t_pred, c->t_q, c->t_anc,
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
-                    c->mrec[0], c->mrec[1], c->arrive,
+                    c->mrec[0], c->mrec[1], c->arrive, c->bar, c->run_args,
                     c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
                     c->g_lbar[1], c->g_theta, c->g_out};
     for (void *p : ptrs)
@@ -402,6 +413,123 @@ int launch_step(pf_ctx *c, const float *frame) {
     return PF_OK;
 }
 
+// Most iterations per k_run launch (bounds a launch's duration).
+constexpr uint32_t kRunMaxSteps = 64;
+// PF_LAUNCH_AUTO uses k_run up to this many workgroups (PEs of all filters):
+// measured on MI355X, its barrier (L2 write-back, arrival count, L2
+// invalidate) costs less than a launch boundary for small contexts (1 x 4 x
+// 256: 10.2 vs 11.5 us per iteration; 1 x 16 x 1024: 13.8 vs 16.6) and more
+// for large ones (1 x 128 x 4096: 30.8 vs 29.7; 4 x 64 x 4096: 39.5 vs 33.5).
+constexpr uint64_t kRunAutoMaxPE = 64;
+
+// Whether the next iterations may run as k_run launches: the context fits
+// (run_fn) and no per-iteration hook is active (gradient tape, forced choices).
+bool run_allowed(const pf_ctx *c) {
+    return c->run_fn && !c->g_cap && !c->force_anc && !c->force_nex;
+}
+
+// n iterations on frames + i * stride.  Iterations run in k_run launches of
+// up to kRunMaxSteps (never across a rebuild of the ring table); a lone
+// iteration, or any iteration while run_allowed is false, is a k_step launch.
+// With ms_out, each launch is timed by a pair of events on the stream and
+// every iteration of it is given the launch's time divided by its length.
+int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out) {
+    const bool timed = ms_out != nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<uint32_t> len_of;   // iterations of each timed launch
+    int rc = PF_OK;
+    uint32_t done = 0;
+    while (rc == PF_OK && done < n) {
+        const uint64_t k = c->step + 1;
+        if (k > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            if (hipEventCreate(&e0) != hipSuccess) {
+                rc = PF_EHIP;
+                break;
+            }
+            ev.push_back(e0);
+            if (hipEventCreate(&e1) != hipSuccess) {
+                rc = PF_EHIP;
+                break;
+            }
+            ev.push_back(e1);
+            if (hipEventRecord(e0, c->stream) != hipSuccess) {
+                rc = PF_EHIP;
+                break;
+            }
+        }
+        uint32_t len = 1;
+        if (run_allowed(c)) {
+            rc = ensure_ring(c, k);
+            if (rc != PF_OK) break;
+            len = n - done < kRunMaxSteps ? n - done : kRunMaxSteps;
+            if (c->ring_valid && c->ring_tab) {
+                const uint64_t room = c->ring_base + kRingSteps - k;
+                if (len > room) len = (uint32_t)room;
+            }
+            if (k + len - 1 > 0xFFFFFFFFull) len = (uint32_t)(0xFFFFFFFFull - k + 1);
+        }
+        const float *frame = frames + (size_t)done * stride;
+        if (len == 1) {
+            rc = launch_step(c, frame);
+        } else {
+            RunPrep pr;
+            memset(&pr, 0, sizeof(pr));
+            pr.a = make_args(c, k, frame);
+            pr.frames = frame;
+            pr.stride = stride;
+            pr.ring0 = pr.a.ring;
+            for (int b = 0; b < 2; ++b) {
+                pr.prop[b] = c->prop[b];
+                pr.anc[b] = c->anc[b];
+                pr.rec[b] = c->rec[b];
+            }
+            pr.cur = (uint32_t)c->cur;
+            pr.n = len;
+            pr.fm = (uint32_t)c->FM;
+            pr.F = c->cfg.n_filters;
+            pr.out = c->run_args;
+            pr.bar = c->bar;
+            const uint32_t threads = len > pr.F ? len : pr.F;
+            (void)hipGetLastError();   // clear errors of earlier, unrelated calls
+            hipLaunchKernelGGL(k_run_prep, dim3((threads + 63) / 64), dim3(64), 0, c->stream, pr);
+            if (hipGetLastError() != hipSuccess) rc = PF_EHIP;
+            RunArgs r;
+            r.args = c->run_args;
+            r.n = len;
+            r.bar = c->bar;
+            r.timeout = c->bar_timeout;
+            void *args[] = {&r};
+            if (rc == PF_OK &&
+                hipLaunchCooperativeKernel(c->run_fn, dim3((uint32_t)c->FM), dim3(c->block), args,
+                                           (unsigned)c->lds, c->stream) != hipSuccess)
+                rc = PF_EHIP;
+            if (rc == PF_OK)
+                for (uint32_t i = 0; i < len; ++i) advance(c, k + i);
+        }
+        if (rc == PF_OK && timed) {
+            if (hipEventRecord(e1, c->stream) != hipSuccess) rc = PF_EHIP;
+            len_of.push_back(len);
+        }
+        if (rc == PF_OK) done += len;
+    }
+    if (timed) {
+        if (rc == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = PF_EHIP;
+        uint32_t it = 0;
+        for (size_t l = 0; rc == PF_OK && l < len_of.size(); ++l) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]) != hipSuccess) {
+                rc = PF_EHIP;
+                break;
+            }
+            for (uint32_t i = 0; i < len_of[l]; ++i) ms_out[it++] = ms / (float)len_of[l];
+        }
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,6 +543,7 @@ const char *pf_strerror(int code) {
         case PF_ENUMERIC: return "NaN log-weight encountered (sticky)";
         case PF_ESTATE: return "call out of order";
         case PF_EUNSUPPORTED: return "size beyond the limits of this build";
+        case PF_ETIMEOUT: return "a barrier between workgroups timed out (sticky)";
         default: return "unknown error";
     }
 }
@@ -516,6 +645,37 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
                 hipSuccess)
             rc = PF_EHIP;
     }
+    if (rc == PF_OK && !c->d_dbg && !c->mrec[0] &&
+        (cfg->launch == PF_LAUNCH_PERSISTENT ||
+         (cfg->launch == PF_LAUNCH_AUTO && c->FM <= kRunAutoMaxPE))) {
+        // k_run needs every workgroup of the context resident at once.  Its
+        // variants must not use private (scratch) memory: the dispatcher may
+        // hold back waves of a kernel whose scratch is not yet allocated, and
+        // waves waiting at the barrier would then wait for waves that cannot
+        // start
+        void *fn = pick_run_kernel(c->ppt, c->half, cfg->lik_mode);
+        int dev = 0, coop = 0, cus = 0, rate_khz = 0, per_cu = 0;
+        hipFuncAttributes fa;
+        memset(&fa, 0, sizeof(fa));
+        if (fn && hipFuncGetAttributes(&fa, fn) == hipSuccess && fa.localSizeBytes == 0 &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds) ==
+                hipSuccess &&
+            hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ==
+                hipSuccess &&
+            hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)c->block, c->lds) ==
+                hipSuccess &&
+            coop && rate_khz > 0 && (uint64_t)per_cu * (uint64_t)cus >= c->FM) {
+            rc = dev_alloc(&c->bar, F);
+            if (rc == PF_OK) rc = dev_alloc(&c->run_args, kRunMaxSteps);
+            c->run_fn = fn;
+            c->bar_timeout = (unsigned long long)rate_khz * 2000ull;   // 2 s
+        }
+        (void)hipGetLastError();
+    }
+    if (rc == PF_OK && cfg->launch == PF_LAUNCH_PERSISTENT && !c->run_fn) rc = PF_EUNSUPPORTED;
     if (rc == PF_OK) {
         if (hipMemcpyAsync(d_truth, truth, 5 * F * sizeof(float), hipMemcpyHostToDevice,
                            c->stream) != hipSuccess ||
@@ -556,38 +716,20 @@ int pf_step(pf_ctx *c, const float *d_frame) {
 
 int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride) {
     if (!c || (!d_frames && n_steps)) return PF_EINVAL;
-    for (uint32_t i = 0; i < n_steps; ++i) {
-        const int rc = launch_step(c, d_frames + (size_t)i * frame_stride);
-        if (rc != PF_OK) return rc;
-    }
-    return PF_OK;
+    return run_steps(c, d_frames, n_steps, frame_stride, nullptr);
 }
 
 int pf_run_timed(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
                  float *host_ms_out) {
     if (!c || !host_ms_out || (!d_frames && n_steps)) return PF_EINVAL;
     if (n_steps == 0) return PF_OK;
-    hipEvent_t *ev = (hipEvent_t *)calloc(2 * (size_t)n_steps, sizeof(hipEvent_t));
-    if (!ev) return PF_ENOMEM;
-    int rc = PF_OK;
-    uint32_t made = 0;
-    for (; made < 2 * n_steps; ++made)
-        if (hipEventCreate(&ev[made]) != hipSuccess) {
-            rc = PF_EHIP;
-            break;
-        }
-    for (uint32_t i = 0; rc == PF_OK && i < n_steps; ++i) {
-        if (hipEventRecord(ev[2 * i], c->stream) != hipSuccess) rc = PF_EHIP;
-        if (rc == PF_OK) rc = launch_step(c, d_frames + (size_t)i * frame_stride);
-        if (rc == PF_OK && hipEventRecord(ev[2 * i + 1], c->stream) != hipSuccess) rc = PF_EHIP;
-    }
-    if (rc == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = PF_EHIP;
-    for (uint32_t i = 0; rc == PF_OK && i < n_steps; ++i)
-        if (hipEventElapsedTime(&host_ms_out[i], ev[2 * i], ev[2 * i + 1]) != hipSuccess)
-            rc = PF_EHIP;
-    for (uint32_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
-    free(ev);
-    return rc;
+    return run_steps(c, d_frames, n_steps, frame_stride, host_ms_out);
+}
+
+int pf_run_info(const pf_ctx *c, uint32_t *host_multi) {
+    if (!c || !host_multi) return PF_EINVAL;
+    *host_multi = c->run_fn ? 1u : 0u;
+    return PF_OK;
 }
 
 int pf_exchange(pf_ctx *c, int64_t *d_src_map) {
@@ -651,7 +793,10 @@ int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
                     for (int d = 0; d < 5; ++d) o->x_pe[5 * i + d] = rec[i].xhat[d];
             }
         o->step = c->step;
-        if (err) rc = PF_ENUMERIC;
+        if (err & kErrBarrier)
+            rc = PF_ETIMEOUT;
+        else if (err)
+            rc = PF_ENUMERIC;
     }
     free(e);
     free(nex);

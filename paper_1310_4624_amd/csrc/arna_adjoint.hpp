@@ -78,7 +78,7 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
     // thread stages the ancestors, the adjoints of its resampled slots and its
     // part of the image tile, centred on this PE's estimate of step k (the
     // mean of its propagated particles).
-    if (wave == 0) prologue_wave(a, f, m, &pro);
+    if (wave == 0) prologue_wave(a, f, m, &pro, threadIdx.x);
     if (wave == (B > kWave ? 1u : 0u)) {
         if (last) {
             // exp(L_p - log sum_m exp(L_m)) over the records of step k
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
     __syncthreads();
     const Prologue p = pro;
     const float lbar = (float)lbar_sh;
-    if (p.nex) build_receive_map(recv, p, np);
+    if (p.nex) build_receive_map(recv, p, np, threadIdx.x);
     // runs of equal ancestors: particle i's offspring are slots [rs[i], re[i])
     for (uint32_t s = tid; s < np; s += B) {
         const uint32_t ai = ancs[s];

@@ -1,6 +1,6 @@
 // arna_kernels.hpp -- the kernels of the ARNA particle-filter step for gfx950
 // and the device-side argument structures they share with the host runtime
-// (arna.hip).  Included by arna.hip only.
+// (arna.hip).  Included by arna.hip and arna_run.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,17 +91,53 @@ struct Prologue {
 //   L_glob = log sum_m W^(m)_{k-1},  P_m = floor(exp(L_m - max L) 2^20),
 //   S = sum P, D = sum P^2  ->  N_ex (Eq. 3 with PE_eff = S^2 / D).
 // Lane 0 writes the result to `out`.
-__device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+__device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
+                              const uint32_t tid) {
+    // Latency first: the ring predecessor is loaded with the records, this
+    // PE's exchange offset is drawn while they are in flight, and the log
+    // masses of this PE and of pred are taken from the lanes that loaded them
+    // (a bit copy: the same values a second read would give).
+    constexpr int kCached = 4;   // record chunks kept in registers (M <= 256)
+    const uint32_t lane = tid & (kWave - 1);
     const uint32_t M = a.M;
     const pf_pe_record *R = a.rin + (size_t)f * M;
-    double lmax = -INFINITY;
-    for (uint32_t i = lane; i < M; i += kWave) lmax = fmax(lmax, R[i].log_mass);
+    const uint32_t pred =
+        (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
+    double lv[kCached];
+    double lmax = -INFINITY, l_own = 0.0, l_pred = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCached; ++c) {
+        const uint32_t j0 = (uint32_t)c * kWave;
+        lv[c] = -INFINITY;
+        if (j0 < M) {
+            if (j0 + lane < M) lv[c] = R[j0 + lane].log_mass;
+            lmax = fmax(lmax, lv[c]);
+            if ((m & ~(kWave - 1)) == j0) l_own = __shfl(lv[c], (int)(m & (kWave - 1)), kWave);
+            if ((pred & ~(kWave - 1)) == j0) l_pred = __shfl(lv[c], (int)(pred & (kWave - 1)), kWave);
+        }
+    }
+    for (uint32_t j0 = kCached * kWave; j0 < M; j0 += kWave) {
+        const double l = (j0 + lane < M) ? R[j0 + lane].log_mass : -INFINITY;
+        lmax = fmax(lmax, l);
+        if ((m & ~(kWave - 1)) == j0) l_own = __shfl(l, (int)(m & (kWave - 1)), kWave);
+        if ((pred & ~(kWave - 1)) == j0) l_pred = __shfl(l, (int)(pred & (kWave - 1)), kWave);
+    }
     lmax = wave_max_d(lmax);
     double acc = 0.0;
     uint64_t S = 0, D = 0;
     if (lmax != -INFINITY) {
-        for (uint32_t i = lane; i < M; i += kWave) {
+        // P_m = floor(exp(L_m - max L) 2^20); slots past M hold -inf: e = 0
+#pragma unroll
+        for (int c = 0; c < kCached; ++c) {
+            if ((uint32_t)c * kWave < M) {
+                const double e = exp(lv[c] - lmax);
+                acc += e;
+                const uint64_t P = (uint64_t)floor(e * 1048576.0);
+                S += P;
+                D += P * P;
+            }
+        }
+        for (uint32_t i = kCached * kWave + lane; i < M; i += kWave) {
             const double e = exp(R[i].log_mass - lmax);
             acc += e;
             const uint64_t P = (uint64_t)floor(e * 1048576.0);
@@ -114,7 +150,7 @@ __device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologu
     D = wave_sum_u64(D);
     if (lane == 0) {
         Prologue p;
-        p.pred = (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
+        p.pred = pred;
         p.nex = exchange_count(S, D, M, a.np, a.mode, (int)a.first, a.fixed_nex, a.initial_nex,
                                a.cutoff_ppm);
         if (a.force_nex) p.nex = a.force_nex[f];
@@ -124,18 +160,19 @@ __device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologu
             p.lam_own = 0.f;
             p.lam_pred = 0.f;
         } else {
-            p.lam_own = (float)(R[m].log_mass - lglob);
-            p.lam_pred = (float)(R[p.pred].log_mass - lglob);
+            p.lam_own = (float)(l_own - lglob);
+            p.lam_pred = (float)(l_pred - lglob);
         }
         p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-        p.c_pred = mulshift(philox(p.pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
+        p.c_pred = mulshift(philox(pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
         *out = p;
     }
 }
 
 // The prologue from a precomputed master record (lane 0 of one wave).
-__device__ void prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out) {
-    if ((threadIdx.x & (kWave - 1)) != 0) return;
+__device__ void prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
+                                const uint32_t tid) {
+    if ((tid & (kWave - 1)) != 0) return;
     const uint32_t M = a.M;
     const pf_pe_record *R = a.rin + (size_t)f * M;
     const MasterRec mr = a.min[f];
@@ -205,8 +242,9 @@ __global__ __launch_bounds__(256) void k_master(const pf_pe_record *rec, MasterR
 // and refills them with the slots s_t(pred(m)) that pred(m) sends.  The map
 // recv[s_t(m)] = s_t(pred(m)) is built in LDS (0xFFFF = slot keeps its own
 // particle); `recv` must hold 0xFFFF for every slot on entry.
-__device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue &p, uint32_t np) {
-    for (uint32_t t = threadIdx.x; t < p.nex; t += blockDim.x) {
+__device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue &p, uint32_t np,
+                                                  const uint32_t tid) {
+    for (uint32_t t = tid; t < p.nex; t += blockDim.x) {
         const uint32_t dst = (t * np + p.c_own) / p.nex;
         const uint32_t src = (t * np + p.c_pred) / p.nex;
         recv[dst] = (uint16_t)src;
@@ -270,8 +308,8 @@ __device__ __forceinline__ Lds carve(unsigned char *base, uint32_t np) {
 // wave leaves the wave totals in wq[wave][q].
 template <int PPT>
 __device__ __forceinline__ void scan_levels(const uint32_t (&Q)[PPT], uint32_t (&cinc)[PPT],
-                                            uint32_t *wq) {
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+                                            uint32_t *wq, const uint32_t tid) {
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) cinc[q] = wave_incl_scan_u32(Q[q]);
     if (lane == kWave - 1)
@@ -283,8 +321,9 @@ __device__ __forceinline__ void scan_levels(const uint32_t (&Q)[PPT], uint32_t (
 // are scanned across the lanes of every wave at once (lane q 16 + w holds level
 // q of wave w), so no further barrier is needed.
 template <int PPT>
-__device__ __forceinline__ uint32_t scan_finish(uint32_t (&cinc)[PPT], const uint32_t *wq) {
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+__device__ __forceinline__ uint32_t scan_finish(uint32_t (&cinc)[PPT], const uint32_t *wq,
+                                                const uint32_t tid) {
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t nwaves = blockDim.x / kWave;
     const uint32_t lq = lane / 16, lw = lane % 16;
     const uint32_t mine = (lq < (uint32_t)PPT && lw < nwaves) ? wq[lw * 4 + lq] : 0u;
@@ -302,11 +341,12 @@ __device__ __forceinline__ uint32_t scan_finish(uint32_t (&cinc)[PPT], const uin
 // mark[first_offspring(i)] = max(i); `mark` (>= n entries) must be zero.
 template <int PPT>
 __device__ __forceinline__ void mark_offspring(const uint32_t (&Q)[PPT], const uint32_t (&C)[PPT],
-                                               uint32_t n, uint32_t T, uint32_t V, uint32_t *mark) {
+                                               uint32_t n, uint32_t T, uint32_t V, uint32_t *mark,
+                                               const uint32_t tid) {
     const double inv_T = 1.0 / (double)T;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const uint32_t s = threadIdx.x + q * blockDim.x;
+        const uint32_t s = tid + q * blockDim.x;
         if (s < n && Q[q] > 0) {
             const uint32_t j = first_offspring(C[q] - Q[q], n, T, V, inv_T);
             if (j < n) atomicMax(&mark[j], s);
@@ -320,9 +360,10 @@ __device__ __forceinline__ void mark_offspring(const uint32_t (&Q)[PPT], const u
 // wave.  Contains one barrier.
 template <int PPT>
 __device__ __forceinline__ void ancestors_from_marks(const uint32_t *mark, uint32_t n,
-                                                     uint32_t *wtmp, uint32_t (&anc)[PPT]) {
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const uint32_t j0 = threadIdx.x * PPT;
+                                                     uint32_t *wtmp, uint32_t (&anc)[PPT],
+                                                     const uint32_t tid) {
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t j0 = tid * PPT;
     uint32_t run = 0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -346,13 +387,20 @@ enum LikKind { kLikGauss = 0, kLikPoint = 1, kLikPoisson = 2 };
 // One ARNA / RNA iteration; one workgroup = one PE (f, m).  Thread t owns the
 // slots s = t + q B, q < PPT (B = blockDim.x), so every global access of a
 // slot level is coalesced.
-template <int PPT, int HALF, int LIK>
-__device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid) {
+// RES (the multi-iteration kernel): xr holds the thread's resampled particles
+// of the previous iteration (slots t + q B), so when from_regs is set the own
+// slots are not read back from HBM; at the end xr receives the particles the
+// resampling picked for those slots.  The values are those k_step would read
+// back, so both kernels compute the same bits.
+template <int PPT, int HALF, int LIK, bool RES = false>
+__device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
+                                          float (&xr)[PPT][5], const bool from_regs,
+                                          const uint32_t tid) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int P = 2 * HALF + 1;
     const uint32_t M = a.M, np = a.np, N = a.N;
     const uint32_t f = bid / M, m = bid % M;
-    const uint32_t tid = threadIdx.x, B = blockDim.x;
+    const uint32_t B = blockDim.x;
     const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, nwaves = B / kWave;
     Lds L = carve(smem, np);
     uint16_t *recv = L.recv;
@@ -372,10 +420,11 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
     // with the same arithmetic.
     if (wave == 0) {
         if (a.min)
-            prologue_master(a, f, m, L.pro);
+            prologue_master(a, f, m, L.pro, tid);
         else
-            prologue_wave(a, f, m, L.pro);
+            prologue_wave(a, f, m, L.pro, tid);
     }
+    const bool load_own = !(RES && from_regs);
     uint32_t own[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -383,7 +432,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
         own[q] = 0;
         if (s < np) {
             recv[s] = 0xFFFF;
-            own[q] = a.ain[pe_base + s];
+            if (load_own) own[q] = a.ain[pe_base + s];
         }
     }
     int tx0 = 0, ty0 = 0;
@@ -408,7 +457,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
         const uint32_t s = tid + q * B;
         if (s < np)
 #pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pe_base + own[q]];
+            for (int c = 0; c < 5; ++c)
+                x[q][c] = load_own ? a.pin[c * N + pe_base + own[q]] : xr[q][c];
     }
     // Tile pixel i = r kTileCols + c is image pixel (tx0 + c, ty0 + r).  Its
     // first kTileRegs B pixels are loaded into registers now and written to
@@ -471,7 +521,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
     }
     const Prologue p = *L.pro;
     if (p.nex) {
-        build_receive_map(recv, p, np);
+        build_receive_map(recv, p, np, tid);
         __syncthreads();   // barrier 1b: receive map
     }
 
@@ -585,7 +635,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
             if (trace) D->t_q[pe_base + s] = Qv[q];
         }
     }
-    scan_levels<PPT>(Qv, cinc, L.wq);
+    scan_levels<PPT>(Qv, cinc, L.wq, tid);
     uint32_t *mark = (uint32_t *)L.tile;   // the tile is no longer read
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -599,15 +649,15 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
         for (int c = 0; c < 6; ++c) L.wsum[wave * 6 + c] = sums[c];
     }
     __syncthreads();   // barrier 3: wave totals, marks cleared
-    const uint32_t T = scan_finish<PPT>(cinc, L.wq);
+    const uint32_t T = scan_finish<PPT>(cinc, L.wq, tid);
     const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
-    mark_offspring<PPT>(Qv, cinc, np, T, V, mark);
+    mark_offspring<PPT>(Qv, cinc, np, T, V, mark, tid);
     __syncthreads();   // barrier 4: marks complete
 
     // ---- phase 4 (step 7): ancestors as prefix maxima of the marks; only the
     // indices are stored (the propagated particles went out in phase 1).
     uint32_t anc[PPT];
-    ancestors_from_marks<PPT>(mark, np, L.wq, anc);
+    ancestors_from_marks<PPT>(mark, np, L.wq, anc, tid);
     if (a.force_anc) {   // replay of another run's choices (test support)
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
@@ -644,6 +694,26 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
             D->t_v[bid] = V;
         }
     }
+    if (RES) {
+        // the particles of this thread's slots for the next iteration: the
+        // ancestors go through LDS from the thread that found them (slots
+        // t PPT + q) to the slot owners (slots t + q B)
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t j = tid * PPT + q;
+            if (j < np) recv[j] = (uint16_t)anc[q];
+        }
+        __syncthreads();
+        // (every lane assigns all of xr, so its old values die here; lanes
+        // past N_p read slot 0)
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t s = tid + q * B;
+            const uint32_t src = recv[s < np ? s : 0u];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) xr[q][c] = L.st[c * np + src];
+        }
+    }
     if (a.mout) {
         // the last workgroup of the filter to publish its record computes the
         // master step of this iteration (records made visible by the fence
@@ -665,7 +735,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid)
 
 template <int PPT, int HALF, int LIK>
 __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
-    step_body<PPT, HALF, LIK>(a, blockIdx.x);
+    float unused[PPT][5];
+    step_body<PPT, HALF, LIK>(a, blockIdx.x, unused, false, threadIdx.x);
 }
 
 // Several independent filter contexts in one launch: context i owns the
@@ -684,8 +755,62 @@ __global__ __launch_bounds__(1024) void k_step_batch(const StepArgs *args, const
             hi = mid;
     }
     const StepArgs a = args[lo];
-    step_body<PPT, HALF, LIK>(a, blockIdx.x - first[lo]);
+    float unused[PPT][5];
+    step_body<PPT, HALF, LIK>(a, blockIdx.x - first[lo], unused, false, threadIdx.x);
 }
+
+// Several iterations of one context in one launch, each workgroup staying on
+// its PE: the resampled particles of a PE's own slots stay in the registers of
+// their threads from one iteration to the next, so only the N_ex received
+// slots are read back from HBM; the propagated particles, ancestors and
+// records still go out every iteration (the receivers and the next launch read
+// them).  Between iterations the M workgroups of a filter meet at a barrier
+// (all workgroups of the launch must be resident at once: cooperative launch).
+struct RunArgs {
+    const StepArgs *args;         // [n] arguments of iterations k0, k0 + 1, ...
+    uint32_t n;                   // iterations in this launch
+    unsigned long long *bar;      // [F] arrivals at the filter barrier, zero at launch
+    unsigned long long timeout;   // longest wait at a barrier, wall-clock ticks
+};
+
+// What k_run_prep turns into the per-iteration arguments of a k_run launch.
+struct RunPrep {
+    StepArgs a;                   // iteration k0 = a.k (buffers, ring and frame set per iteration)
+    const float *frames;          // frame of iteration k0 + i at frames + i * stride
+    uint64_t stride;
+    const uint16_t *ring0;        // pred(m) rows of iterations k0, k0 + 1, ... (F M each), or NULL
+    float *prop[2];
+    uint16_t *anc[2];
+    pf_pe_record *rec[2];
+    uint32_t cur;                 // buffer index holding iteration k0 - 1
+    uint32_t n, fm, F;
+    StepArgs *out;                // [n]
+    unsigned long long *bar;      // [F], zeroed
+};
+
+__global__ void k_run_prep(RunPrep p) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) {
+        StepArgs a = p.a;
+        const uint32_t in = (p.cur + i) & 1u, out = in ^ 1u;
+        a.pin = p.prop[in];
+        a.ain = p.anc[in];
+        a.rin = p.rec[in];
+        a.pout = p.prop[out];
+        a.aout = p.anc[out];
+        a.rout = p.rec[out];
+        a.ring = p.ring0 ? p.ring0 + (size_t)i * p.fm : nullptr;
+        a.lik.img = p.frames + (size_t)i * p.stride;
+        a.k += i;
+        if (i) a.first = 0u;
+        p.out[i] = a;
+    }
+    if (i < p.F) p.bar[i] = 0ull;
+}
+
+// Error bit set when a barrier wait of k_run exceeds its limit (the launch
+// then ends).
+constexpr uint32_t kErrBarrier = 2u;
 
 // Step 1 for kRingSteps iterations at once: Fisher-Yates (Durstenfeld,
 // i = M-1 .. 1, j = floor(r_i (i + 1) / 2^32)) over the M labels; the ring
@@ -903,11 +1028,11 @@ __global__ __launch_bounds__(256) void k_exchange_map(StepArgs a, int64_t *src) 
     __shared__ Prologue pro;
     __shared__ uint16_t recv[PF_MAX_PER_PE];
     const uint32_t f = blockIdx.x / a.M, m = blockIdx.x % a.M;
-    if (threadIdx.x < kWave) prologue_wave(a, f, m, &pro);
+    if (threadIdx.x < kWave) prologue_wave(a, f, m, &pro, threadIdx.x);
     for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) recv[s] = 0xFFFF;
     __syncthreads();
     const Prologue p = pro;
-    build_receive_map(recv, p, a.np);
+    build_receive_map(recv, p, a.np, threadIdx.x);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) {
         const uint32_t r = recv[s];
@@ -931,12 +1056,12 @@ __global__ __launch_bounds__(1024) void k_resample_q(const uint32_t *q, const ui
         Qv[k] = (s < np) ? q[base + s] : 0u;
         if (s < np) mark[s] = 0;
     }
-    scan_levels<PPT>(Qv, cinc, wq);
+    scan_levels<PPT>(Qv, cinc, wq, threadIdx.x);
     __syncthreads();
-    const uint32_t T = scan_finish<PPT>(cinc, wq);
-    mark_offspring<PPT>(Qv, cinc, np, T, v[blockIdx.x], mark);
+    const uint32_t T = scan_finish<PPT>(cinc, wq, threadIdx.x);
+    mark_offspring<PPT>(Qv, cinc, np, T, v[blockIdx.x], mark, threadIdx.x);
     __syncthreads();
-    ancestors_from_marks<PPT>(mark, np, wq, anc);
+    ancestors_from_marks<PPT>(mark, np, wq, anc, threadIdx.x);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const uint32_t j = threadIdx.x * PPT + k;
@@ -972,3 +1097,9 @@ __global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t
 }
 
 }  // namespace
+
+// k_run<PPT, HALF, LIK> for a context's slots per thread, patch half-width and
+// likelihood mode, or NULL when no variant exists (defined in arna_run.hip,
+// which is compiled on its own).
+void *arna_run_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode);
+

@@ -12,13 +12,13 @@ from . import _native as nat
 CONFIG_KEYS = ("n_filters", "n_pe", "n_per_pe", "width", "height", "patch", "mode",
                "init_mode", "lik_mode", "fixed_ratio", "initial_ratio", "eff_cutoff",
                "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed", "ring_groups",
-               "block_size")
+               "block_size", "launch")
 
 DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
                 mode=nat.PF_MODE_RNA, init_mode=nat.PF_INIT_TRACKING, lik_mode=nat.PF_LIK_PATCH,
                 fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
                 background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1, ring_groups=0,
-                block_size=0)
+                block_size=0, launch=nat.PF_LAUNCH_AUTO)
 
 
 def _ptr(a: np.ndarray):
@@ -105,6 +105,12 @@ class Tracker:
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
                   "pf_run_timed")
         return out
+
+    def multi_iteration(self) -> bool:
+        """Whether run() may use multi-iteration launches (pf_run_info)."""
+        v = ctypes.c_uint32()
+        nat.check(nat.lib().pf_run_info(self._h, ctypes.byref(v)), "pf_run_info")
+        return bool(v.value)
 
     def exchange(self, src_map=None) -> None:
         p = None

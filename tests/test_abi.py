@@ -142,7 +142,12 @@ def test_debug_resample_rejects_bad_offsets_on_host(L):
 
 
 def test_build_flags_target_gfx950_without_packed_fp32():
-    cmd = b.command("/tmp/x.so")
-    assert "--offload-arch=gfx950" in cmd
-    i = cmd.index("-packed-fp32-ops")
-    assert cmd[i - 1] == "-Xclang" and cmd[i - 2] == "-target-feature"
+    cmds = b.commands("/tmp/x.so", "/tmp")
+    assert len(cmds) == 3
+    for cmd in cmds[:2]:                      # both translation units
+        assert "--offload-arch=gfx950" in cmd
+        i = cmd.index("-packed-fp32-ops")
+        assert cmd[i - 1] == "-Xclang" and cmd[i - 2] == "-target-feature"
+    assert "-disable-machine-licm" in cmds[1] and "-disable-machine-licm" not in cmds[0]
+    assert cmds[0][-1].endswith("arna.hip") and cmds[1][-1].endswith("arna_run.hip")
+    assert "-shared" in cmds[2]
