@@ -252,10 +252,11 @@ __device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue
 }
 
 // LDS image tile: 64 x 64 pixels of z - B, zero outside the image.  The row
-// pitch is 11 mod 32 (and mod 64), so the patch origins of a cluster of
-// particles, which differ by a few rows and columns, fall on different LDS
-// banks.
-constexpr int kTileCols = 64, kTilePitch = 75, kTileRows = 64;
+// pitch decides how often the patch reads of a wave's particles, whose patch
+// origins differ by a few rows and columns, meet in the same LDS bank; chosen
+// by measurement on MI355X (one step at 2^20 particles, 4 x 64 x 4096):
+// pitch 65: 37.9 us, 67: 32.9, 69-73: 30.8-30.9, 75: 33.2, 77: 31.0, 79: 33.5.
+constexpr int kTileCols = 64, kTilePitch = 70, kTileRows = 64;
 constexpr int kMaxWaves = 16;
 
 // Dynamic LDS layout of k_step (the tile comes first: its reads use small
