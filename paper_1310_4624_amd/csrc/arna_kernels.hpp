@@ -91,8 +91,8 @@ struct Prologue {
 //   L_glob = log sum_m W^(m)_{k-1},  P_m = floor(exp(L_m - max L) 2^20),
 //   S = sum P, D = sum P^2  ->  N_ex (Eq. 3 with PE_eff = S^2 / D).
 // Lane 0 writes the result to `out`.
-__device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
-                              const uint32_t tid) {
+__device__ Prologue prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
+                                  const uint32_t tid) {
     // Latency first: the ring predecessor is loaded with the records, this
     // PE's exchange offset is drawn while they are in flight, and the log
     // masses of this PE and of pred are taken from the lanes that loaded them
@@ -148,31 +148,35 @@ __device__ void prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologu
     acc = wave_sum(acc);
     S = wave_sum_u64(S);
     D = wave_sum_u64(D);
-    if (lane == 0) {
-        Prologue p;
-        p.pred = pred;
-        p.nex = exchange_count(S, D, M, a.np, a.mode, (int)a.first, a.fixed_nex, a.initial_nex,
-                               a.cutoff_ppm);
-        if (a.force_nex) p.nex = a.force_nex[f];
-        if (p.nex > a.np) p.nex = a.np;
-        const double lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
-        if (lglob == -INFINITY) {
-            p.lam_own = 0.f;
-            p.lam_pred = 0.f;
-        } else {
-            p.lam_own = (float)(l_own - lglob);
-            p.lam_pred = (float)(l_pred - lglob);
-        }
-        p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-        p.c_pred = mulshift(philox(pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-        *out = p;
+    // Every lane finishes the prologue (the wave executes it once either
+    // way) and returns it: its integer fields (pred, N_ex, offsets) are the
+    // same in every lane -- S and D are exact sums -- while the FP64 sum acc,
+    // reduced in a different order in each lane, can differ in the last bit,
+    // so the record other waves read is lane 0's.
+    Prologue p;
+    p.pred = pred;
+    p.nex = exchange_count(S, D, M, a.np, a.mode, (int)a.first, a.fixed_nex, a.initial_nex,
+                           a.cutoff_ppm);
+    if (a.force_nex) p.nex = a.force_nex[f];
+    if (p.nex > a.np) p.nex = a.np;
+    const double lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
+    if (lglob == -INFINITY) {
+        p.lam_own = 0.f;
+        p.lam_pred = 0.f;
+    } else {
+        p.lam_own = (float)(l_own - lglob);
+        p.lam_pred = (float)(l_pred - lglob);
     }
+    p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
+    p.c_pred = mulshift(philox(pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
+    if (lane == 0) *out = p;
+    return p;
 }
 
-// The prologue from a precomputed master record (lane 0 of one wave).
-__device__ void prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
-                                const uint32_t tid) {
-    if ((tid & (kWave - 1)) != 0) return;
+// The prologue from a precomputed master record, computed by every lane of one
+// wave (uniform inputs: every lane gets the same values); lane 0 writes it.
+__device__ Prologue prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
+                                    const uint32_t tid) {
     const uint32_t M = a.M;
     const pf_pe_record *R = a.rin + (size_t)f * M;
     const MasterRec mr = a.min[f];
@@ -197,7 +201,8 @@ __device__ void prologue_master(const StepArgs &a, uint32_t f, uint32_t m, Prolo
     }
     p.c_own = mulshift(philox(m, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
     p.c_pred = mulshift(philox(p.pred, a.k, f, kTagExch << 24, a.key0, a.key1).x, a.np);
-    *out = p;
+    if ((tid & (kWave - 1)) == 0) *out = p;
+    return p;
 }
 
 // Master record of filter f from its M PE records, by the whole workgroup
@@ -251,6 +256,29 @@ __device__ __forceinline__ void build_receive_map(uint16_t *recv, const Prologue
     }
 }
 
+// Receive maps of up to kMapWave entries are built by wave 0 before barrier 1
+// with kMapBatch loads in flight per lane, when the prologue leaves it the
+// time (M <= 64: one record per lane); otherwise by the workgroup after it.
+// Measured on MI355X at 2^20 particles: 4 x 64 x 4096 31.0 -> 30.1 us per
+// step; 1 x 256 x 4096 32.3 -> 33.3 with wave 0's map, hence the M limit.
+constexpr int kMapBatch = 8;
+constexpr uint32_t kMapWave = kMapBatch * kWave;
+__device__ __forceinline__ bool map_by_wave0(uint32_t nex, uint32_t M) {
+    return nex <= kMapWave && M <= kWave;
+}
+
+// Step 3 for one slot: if slot s of PE m is refilled (s = s_t(m) for some
+// t < N_ex), the slot s_t(pred(m)) of pred's resampled block it receives;
+// else 0xFFFF.  The t with floor((t N_p + c_own) / N_ex) = s is the least
+// t >= (s N_ex - c_own) / N_p (at most one: N_ex <= N_p).
+__device__ __forceinline__ uint32_t received_from(uint32_t s, const Prologue &p, uint32_t np) {
+    if (p.nex == 0) return 0xFFFFu;
+    const int64_t num = (int64_t)s * p.nex - (int64_t)p.c_own;
+    const uint64_t t = num <= 0 ? 0u : (uint64_t)((num + np - 1) / np);
+    if (t >= p.nex || (t * np + p.c_own) / p.nex != s) return 0xFFFFu;
+    return (uint32_t)((t * np + p.c_pred) / p.nex);
+}
+
 // LDS image tile: 64 x 64 pixels of z - B, zero outside the image.  The row
 // pitch decides how often the patch reads of a wave's particles, whose patch
 // origins differ by a few rows and columns, meet in the same LDS bank; chosen
@@ -269,7 +297,7 @@ struct Lds {
     uint32_t *wq;      // [16][4] wave totals of Q, per slot level
     float *st;         // [5][np] propagated particles
     uint32_t *cq;      // [np] carried weight, then u, then nothing
-    uint16_t *recv;    // [np] receive map
+    uint16_t *recv;    // [np] per slot: pred's propagated particle it receives, or 0xFFFF
     int32_t *lin;      // [np] (lineage only)
 };
 __host__ __device__ constexpr size_t lds_fixed_bytes() {
@@ -420,10 +448,35 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
     // (x + v); a particle whose patch does not fit in it reads the frame,
     // with the same arithmetic.
     if (wave == 0) {
-        if (a.min)
-            prologue_master(a, f, m, L.pro, tid);
-        else
-            prologue_wave(a, f, m, L.pro, tid);
+        const Prologue p =
+            a.min ? prologue_master(a, f, m, L.pro, tid) : prologue_wave(a, f, m, L.pro, tid);
+        // Step 3's receive map, before this wave's own loads (the other waves
+        // are drawing normals; wave 0 has slack until they reach barrier 1):
+        // slot s_t(m) gets pred's propagated particle ain[s_t(pred)], the
+        // ancestor lookup done here so that phase 1 needs a single load per
+        // received component.  Lanes clear slots that other lanes then fill:
+        // wavefront-scope release / acquire around a wave barrier order them.
+        if (M <= kWave) {   // else each thread clears its own slots
+            for (uint32_t s = lane; s < np; s += kWave) recv[s] = 0xFFFF;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // up to kMapBatch ancestor loads in flight per lane before any is used
+        if (map_by_wave0(p.nex, M)) {
+            const uint32_t pred_base = (f * M + p.pred) * np;
+            uint16_t got[kMapBatch];
+#pragma unroll
+            for (int j = 0; j < kMapBatch; ++j) {
+                const uint32_t t = lane + (uint32_t)j * kWave;
+                if (t < p.nex) got[j] = a.ain[pred_base + (t * np + p.c_pred) / p.nex];
+            }
+#pragma unroll
+            for (int j = 0; j < kMapBatch; ++j) {
+                const uint32_t t = lane + (uint32_t)j * kWave;
+                if (t < p.nex) recv[(t * np + p.c_own) / p.nex] = got[j];
+            }
+        }
     }
     const bool load_own = !(RES && from_regs);
     uint32_t own[PPT];
@@ -431,10 +484,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
     for (int q = 0; q < PPT; ++q) {
         const uint32_t s = tid + q * B;
         own[q] = 0;
-        if (s < np) {
-            recv[s] = 0xFFFF;
-            if (load_own) own[q] = a.ain[pe_base + s];
-        }
+        if (s < np && load_own) own[q] = a.ain[pe_base + s];
+        if (s < np && M > kWave) recv[s] = 0xFFFF;   // else wave 0 clears the map
     }
     int tx0 = 0, ty0 = 0;
     bool tile_on = false, tile_inside = false;
@@ -509,8 +560,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
                 in ? a.lik.img[(size_t)v * a.lik.W + u] - a.lik.bg : 0.f;
         }
     }
-    __syncthreads();   // barrier 1: prologue, tile and wave 0's normals visible,
-                       // receive map cleared
+    __syncthreads();   // barrier 1: prologue, receive map, tile and wave 0's
+                       // normals visible
     if (helpers && wave == 0) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
@@ -521,28 +572,30 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
         }
     }
     const Prologue p = *L.pro;
-    if (p.nex) {
-        build_receive_map(recv, p, np, tid);
-        __syncthreads();   // barrier 1b: receive map
+    if (p.nex && !map_by_wave0(p.nex, M)) {
+        // the whole workgroup fills the receive map
+        const uint32_t pb = (f * M + p.pred) * np;
+        for (uint32_t t = tid; t < p.nex; t += B)
+            recv[(t * np + p.c_own) / p.nex] = a.ain[pb + (t * np + p.c_pred) / p.nex];
+        __syncthreads();   // barrier 1b: receive map (when not wave 0's)
     }
 
-    // ---- phase 1 (steps 3-5 P): received slots are refetched from pred(m);
-    // propagate; stage in LDS.  A thread reads back only its own slots, so
-    // the likelihood follows without a barrier.
+    // ---- phase 1 (steps 3-5 P): received slots are refetched from pred(m)
+    // (all of a thread's loads issued before the first is used); propagate;
+    // stage in LDS.  A thread reads back only its own slots, so the
+    // likelihood follows without a barrier.
+    const uint32_t pred_base = (f * M + p.pred) * np;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const uint32_t s = tid + q * B;
         if (s >= np) continue;
         uint32_t gsrc = pe_base + s;
         float lam = p.lam_own;
-        const uint32_t r = p.nex ? recv[s] : 0xFFFFu;
-        if (r != 0xFFFFu) {
-            const uint32_t pred_base = (f * M + p.pred) * np;
-            gsrc = pred_base + r;
+        const uint32_t pq = p.nex ? recv[s] : 0xFFFFu;
+        if (pq != 0xFFFFu) {
+            for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pred_base + pq];
             lam = p.lam_pred;
-            const uint32_t pa = a.ain[gsrc];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) x[q][c] = a.pin[c * N + pred_base + pa];
+            if (lin_in || trace) gsrc = pred_base + received_from(s, p, np);
         }
         if (lin_in) L.lin[s] = lin_in[gsrc];
         if (trace) {
@@ -686,12 +739,15 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
         r.lstar = lstar;
         r.total_q = T;
         a.rout[bid] = r;
+        // (the prologue record is read again from LDS, where it stays for
+        // the whole iteration: nothing keeps it in registers until here)
+        const Prologue *pr = L.pro;
         if (m == 0) {
-            a.nex_used[f] = p.nex;
-            if (a.nex_rec) a.nex_rec[f] = p.nex;
+            a.nex_used[f] = pr->nex;
+            if (a.nex_rec) a.nex_rec[f] = pr->nex;
         }
         if (trace) {
-            D->t_pred[bid] = p.pred;
+            D->t_pred[bid] = pr->pred;
             D->t_v[bid] = V;
         }
     }

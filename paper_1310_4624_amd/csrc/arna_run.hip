@@ -67,7 +67,8 @@ __global__ __launch_bounds__(1024) void k_run(RunArgs r) {
         uint32_t b = bid, w = wv;
         __asm__ volatile("" : "+s"(kp), "+s"(b), "+s"(w));
         ConstArgs ap = (ConstArgs)(uintptr_t)(kp->args + i);
-        const uint32_t t = w * kWave + __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        uint32_t t = w * kWave + __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        __asm__ volatile("" : "+v"(t));   // else t & 63 folds back to the hoisted lane id
         StepArgs a = *ap;
         // never set for a multi-iteration launch (the host checks); known
         // null here, the code paths they guard drop out
