@@ -115,7 +115,8 @@ def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int, ring_
 def grad_leg(workload: str, frames_n: int, seed: int):
     """Cost of the gradient: K iterations forward, then the same K iterations
     recorded plus the reverse sweep (pf_grad_end), on the same frames and
-    start.  Both regions are bracketed by events on the library's stream."""
+    start.  Both regions are bracketed by events on the library's stream;
+    each is measured three times and the medians are reported."""
     import torch
     from paper_1310_4624_amd import Tracker, synth
 
@@ -133,26 +134,34 @@ def grad_leg(workload: str, frames_n: int, seed: int):
     tr.close()
     torch.cuda.synchronize()
 
-    tr = Tracker(cfg, truth)
-    ev[0].record(stream)
-    tr.run(frames)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    tr.close()
-    tr = Tracker(cfg, truth)
-    torch.cuda.synchronize()
-    ev[2].record(stream)
-    tr.grad_begin(frames_n)
-    tr.run(frames)
-    res = tr.grad_end(frames)
-    ev[3].record(stream)
-    torch.cuda.synchronize()
-    tr.close()
-    fwd = ev[0].elapsed_time(ev[1])
-    both = ev[2].elapsed_time(ev[3])
+    # three measurements of each region (a context made afresh each time);
+    # the medians are reported
+    fwds, boths = [], []
+    for _ in range(3):
+        tr = Tracker(cfg, truth)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        tr.run(frames)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        tr.close()
+        tr = Tracker(cfg, truth)
+        torch.cuda.synchronize()
+        ev[2].record(stream)
+        tr.grad_begin(frames_n)
+        tr.run(frames)
+        res = tr.grad_end(frames)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        tr.close()
+        fwds.append(ev[0].elapsed_time(ev[1]))
+        boths.append(ev[2].elapsed_time(ev[3]))
+    fwd = sorted(fwds)[1]
+    both = sorted(boths)[1]
     return {"workload": workload, "frames": frames_n,
             "n_particles": cfg["n_filters"] * cfg["n_pe"] * cfg["n_per_pe"],
             "fwd_ms": fwd, "fwd_bwd_ms": both, "fwd_bwd_over_fwd": both / fwd,
+            "fwd_ms_runs": fwds, "fwd_bwd_ms_runs": boths,
             "J": res["J"].tolist(), "dJ_dtheta": res["grad"].tolist(),
             "theta": ["psf_sigma", "I0", "q"]}
 

@@ -867,7 +867,7 @@ int pf_grad_value(pf_ctx *c, double *host_J) {
     if (!c->g_cap) return PF_ESTATE;
     const uint32_t F = c->cfg.n_filters;
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, c->g_len,
+    hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(kGradReduceThreads), 0, c->stream, c->g_rec, c->g_len,
                        (const double *)nullptr, c->cfg.n_pe, c->cfg.n_per_pe, (uint32_t)c->FM,
                        c->g_out);
     HIP_OK(hipGetLastError());
@@ -943,7 +943,7 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
         }
         if (rc == PF_OK) {
             (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-            hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(256), 0, c->stream, c->g_rec, K,
+            hipLaunchKernelGGL(k_grad_reduce, dim3(F), dim3(kGradReduceThreads), 0, c->stream, c->g_rec, K,
                                (const double *)c->g_theta, c->cfg.n_pe, c->cfg.n_per_pe,
                                (uint32_t)FM, c->g_out);
             if (hipGetLastError() != hipSuccess ||

@@ -215,23 +215,31 @@ __global__ __launch_bounds__(1024) void k_adjoint(StepArgs a, AdjArgs g) {
 }
 
 // Per filter: J = sum_k (log sum_m W^(m)_k - log N_p) over the recorded
-// records rec[1..K] (one iteration per thread), and the sums over the PEs of
-// the per-PE gradient parts.  out[f] = (J, dJ/dsigma, dJ/dI0, dJ/dq); with
-// theta == NULL only J.
-__global__ __launch_bounds__(256) void k_grad_reduce(const pf_pe_record *rec, uint32_t K,
-                                                     const double *theta, uint32_t M,
-                                                     uint32_t np, uint32_t FM, double *out) {
-    __shared__ double red[kRedDoubles];
+// records rec[1..K], and the sums over the PEs of the per-PE gradient parts.
+// out[f] = (J, dJ/dsigma, dJ/dI0, dJ/dq); with theta == NULL only J.  One
+// workgroup of kGradReduceThreads per filter: each wave takes one iteration at
+// a time, its lanes the M records (wave reductions, no barrier per
+// iteration).
+constexpr uint32_t kGradReduceThreads = 1024;
+__global__ __launch_bounds__(kGradReduceThreads) void k_grad_reduce(
+    const pf_pe_record *rec, uint32_t K, const double *theta, uint32_t M, uint32_t np, uint32_t FM,
+    double *out) {
+    __shared__ double red[kMaxWaves * 4];
     const uint32_t f = blockIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t nwaves = blockDim.x / kWave;
     double v[4] = {0, 0, 0, 0};
-    for (uint32_t k = 1 + threadIdx.x; k <= K; k += blockDim.x) {
+    for (uint32_t k = 1 + wave; k <= K; k += nwaves) {
         const pf_pe_record *R = rec + (size_t)k * FM + (size_t)f * M;
         double lmax = -INFINITY;
-        for (uint32_t i = 0; i < M; ++i) lmax = fmax(lmax, R[i].log_mass);
+        for (uint32_t i = lane; i < M; i += kWave) lmax = fmax(lmax, R[i].log_mass);
+        lmax = wave_max_d(lmax);
         double acc = 0.0;
         if (lmax != -INFINITY)
-            for (uint32_t i = 0; i < M; ++i) acc += exp(R[i].log_mass - lmax);
-        v[0] += (lmax == -INFINITY) ? -INFINITY : lmax + log(acc) - log((double)np);
+            for (uint32_t i = lane; i < M; i += kWave) acc += exp(R[i].log_mass - lmax);
+        acc = wave_sum(acc);
+        if (lane == 0)
+            v[0] += (lmax == -INFINITY) ? -INFINITY : lmax + log(acc) - log((double)np);
     }
     if (theta)
         for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
