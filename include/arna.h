@@ -49,13 +49,11 @@ enum { PF_MODE_RNA = 0, PF_MODE_ARNA = 1 };
 enum { PF_INIT_TRACKING = 0, PF_INIT_INFOSHARE = 1 };
 enum { PF_LIK_PATCH = 0, PF_LIK_POINT = 1, PF_LIK_POISSON = 2 };
 /* How pf_run launches its iterations (pf_config.launch). */
-enum { PF_LAUNCH_AUTO = 0,        /* multi-iteration launches for contexts of at most 64
-                                     PEs in all (where they are faster), else one launch
-                                     per iteration */
+enum { PF_LAUNCH_AUTO = 0,        /* the library's choice: currently one launch per
+                                     iteration (see pf_config.launch) */
        PF_LAUNCH_STEPWISE = 1,    /* one launch per iteration */
-       PF_LAUNCH_PERSISTENT = 2   /* multi-iteration launches whatever the size; pf_init
-                                     fails with PF_EUNSUPPORTED when the context cannot use
-                                     them */ };
+       PF_LAUNCH_PERSISTENT = 2   /* multi-iteration launches; pf_init fails with
+                                     PF_EUNSUPPORTED when the context cannot use them */ };
 
 /* Debug flags (pf_config.debug). */
 enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the last step */
@@ -116,7 +114,10 @@ typedef struct {
                                  * iteration.  Iterations that record a gradient tape or
                                  * replay forced choices always run one launch each.  The
                                  * barrier costs less than a launch boundary only for small
-                                 * contexts, hence the AUTO rule. */
+                                 * contexts (about 10-15% faster up to 64 PEs), and the
+                                 * cooperative launch it needs costs about 1 ms once the
+                                 * process uses three or more other streams, so AUTO does
+                                 * not choose it. */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;

@@ -125,6 +125,12 @@ struct pf_batch {
     hipStream_t stream;
     StepArgs *d_args;                    // [steps][n_batched], grown on demand
     size_t args_cap;
+    // The groups share nothing, so they run side by side: group i (and the
+    // solo contexts after the groups) on workers[i % workers.size()], forked
+    // from and joined back to `stream` with events at every run.
+    std::vector<hipStream_t> workers;
+    hipEvent_t ev_fork;
+    std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -413,14 +419,18 @@ int launch_step(pf_ctx *c, const float *frame) {
     return PF_OK;
 }
 
+// Streams a batch spreads its groups over (HIP's default of four hardware
+// queues per process).
+constexpr size_t kBatchStreams = 4;
+
 // Most iterations per k_run launch (bounds a launch's duration).
 constexpr uint32_t kRunMaxSteps = 64;
-// PF_LAUNCH_AUTO uses k_run up to this many workgroups (PEs of all filters):
-// measured on MI355X, its barrier (L2 write-back, arrival count, L2
-// invalidate) costs less than a launch boundary for small contexts (1 x 4 x
-// 256: 10.2 vs 11.5 us per iteration; 1 x 16 x 1024: 13.8 vs 16.6) and more
-// for large ones (1 x 128 x 4096: 30.8 vs 29.7; 4 x 64 x 4096: 39.5 vs 33.5).
-constexpr uint64_t kRunAutoMaxPE = 64;
+// PF_LAUNCH_AUTO launches one kernel per iteration.  Measured on MI355X, k_run
+// is faster only for small contexts (1 x 4 x 256: 10.2 vs 11.5 us per
+// iteration; 1 x 16 x 1024: 13.8 vs 16.6; 4 x 64 x 4096: 39.5 vs 33.5), and
+// its cooperative launch costs about a millisecond once the process has three
+// or more other streams (a batch of 64 small contexts stepped one after
+// another: 54 ms instead of 31 ms), so it is used only on request.
 
 // Whether the next iterations may run as k_run launches: the context fits
 // (run_fn) and no per-iteration hook is active (gradient tape, forced choices).
@@ -645,9 +655,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
                 hipSuccess)
             rc = PF_EHIP;
     }
-    if (rc == PF_OK && !c->d_dbg && !c->mrec[0] &&
-        (cfg->launch == PF_LAUNCH_PERSISTENT ||
-         (cfg->launch == PF_LAUNCH_AUTO && c->FM <= kRunAutoMaxPE))) {
+    if (rc == PF_OK && !c->d_dbg && !c->mrec[0] && cfg->launch == PF_LAUNCH_PERSISTENT) {
         // k_run needs every workgroup of the context resident at once.  Its
         // variants must not use private (scratch) memory: the dispatcher may
         // hold back waves of a kernel whose scratch is not yet allocated, and
@@ -1019,6 +1027,25 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
                                                (int)g.lds) != hipSuccess)
             rc = PF_EHIP;
     }
+    b->ev_fork = nullptr;
+    const size_t lanes = b->groups.size() + b->solo.size();
+    const size_t nw = lanes < kBatchStreams ? (lanes ? lanes : 1) : kBatchStreams;
+    if (rc == PF_OK && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess)
+        rc = PF_EHIP;
+    for (size_t w = 0; w < nw && rc == PF_OK; ++w) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            rc = PF_EHIP;
+            break;
+        }
+        b->workers.push_back(st);
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            rc = PF_EHIP;
+            break;
+        }
+        b->ev_join.push_back(ev);
+    }
     if (rc != PF_OK) {
         pf_batch_destroy(b);
         return rc;
@@ -1093,7 +1120,7 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
     HIP_OK(hipStreamSynchronize(b->stream));   // earlier runs may still read d_args
     HIP_OK(hipMemcpy(b->d_args, args.data(), args.size() * sizeof(StepArgs),
                      hipMemcpyHostToDevice));
-    // graph mode: the launches are captured on a private stream (the legacy
+    // graph mode: the launches are captured from a private stream (the legacy
     // stream cannot be captured) and the graph is launched on the batch's
     const hipStream_t run_stream = b->stream;
     hipStream_t cap = nullptr;
@@ -1105,29 +1132,39 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
             (void)hipStreamDestroy(cap);
             return PF_EHIP;
         }
-        b->stream = cap;
-        for (pf_ctx *c : b->ctx) c->stream = cap;
     }
+    const hipStream_t base = use_graph ? cap : run_stream;
+    const size_t nw = b->workers.size();
     int rc = PF_OK;
+    // fork: the workers start after what `base` holds
+    if (hipEventRecord(b->ev_fork, base) != hipSuccess) rc = PF_EHIP;
+    for (size_t w = 0; w < nw && rc == PF_OK; ++w)
+        if (hipStreamWaitEvent(b->workers[w], b->ev_fork, 0) != hipSuccess) rc = PF_EHIP;
+    // every context enqueues on its lane's worker (ring rebuilds, solo steps)
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        for (uint32_t i : b->groups[gi].members) b->ctx[i]->stream = b->workers[gi % nw];
+    for (size_t si = 0; si < b->solo.size(); ++si)
+        b->ctx[b->solo[si]]->stream = b->workers[(b->groups.size() + si) % nw];
     for (uint32_t t = 0; t < n_steps && rc == PF_OK; ++t) {
         for (auto &r : rings[t]) {
             rc = launch_ring(b->ctx[r.first], r.second);
             if (rc != PF_OK) break;
         }
         uint32_t slot = 0;
-        for (auto &g : b->groups) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
             if (rc != PF_OK) break;
+            auto &g = b->groups[gi];
             const StepArgs *ga = b->d_args + (size_t)t * nb + slot;
             uint32_t cnt = (uint32_t)g.members.size();
             void *kargs[] = {&ga, &g.d_first, &cnt};
-            if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds, b->stream) !=
-                hipSuccess)
+            if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds,
+                                b->workers[gi % nw]) != hipSuccess)
                 rc = PF_EHIP;
             for (uint32_t i : g.members) {
                 pf_ctx *c = b->ctx[i];
                 const uint64_t k = c->step + 1;
-                uint64_t base;
-                plan_ring(c, k, false, &base);   // the table state the host pass assumed
+                uint64_t base_k;
+                plan_ring(c, k, false, &base_k);   // the table state the host pass assumed
                 advance(c, k);
             }
             slot += cnt;
@@ -1137,10 +1174,15 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
             rc = launch_step(b->ctx[i], d_frames[i] + (size_t)t * frame_stride[i]);
         }
     }
+    // join: `base` continues after every worker (also after an error, so the
+    // capture can end and later work stays ordered)
+    for (size_t w = 0; w < nw; ++w)
+        if (hipEventRecord(b->ev_join[w], b->workers[w]) != hipSuccess ||
+            hipStreamWaitEvent(base, b->ev_join[w], 0) != hipSuccess)
+            rc = PF_EHIP;
+    for (pf_ctx *c : b->ctx) c->stream = run_stream;
     if (use_graph) {
         const hipError_t e = hipStreamEndCapture(cap, &graph);
-        b->stream = run_stream;
-        for (pf_ctx *c : b->ctx) c->stream = run_stream;
         if (rc == PF_OK && e != hipSuccess) rc = PF_EHIP;
         if (rc == PF_OK) {
             hipGraphExec_t exec = nullptr;
@@ -1160,6 +1202,12 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
 void pf_batch_destroy(pf_batch *b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t st : b->workers) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (auto &g : b->groups)
         if (g.d_first) (void)hipFree(g.d_first);
     if (b->d_args) (void)hipFree(b->d_args);

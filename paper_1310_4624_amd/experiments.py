@@ -139,9 +139,15 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
                 for i, (c, t, _) in enumerate(seqs)]
 
     out = {"n_seq": n_seq, "frames": frames, "particle_steps": total}
-    # warm-up: load every kernel variant once
+    # warm-up: load every kernel variant once, batched and per context (two
+    # iterations, so that multi-iteration launches are loaded too)
     trs = make()
     Batch(trs).run([d[:1] for d in dev])
+    for t in trs:
+        t.close()
+    trs = make()
+    for t, d in zip(trs, dev):
+        t.run(d[:2])
     for t in trs:
         t.close()
     trs = make()

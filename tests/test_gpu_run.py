@@ -198,9 +198,8 @@ def test_contexts_that_cannot_stay_resident_are_refused():
     t = p.Tracker(dict(c, launch=PERSISTENT), z)
     assert t.multi_iteration()
     t.close()
-    # AUTO: multi-iteration launches up to 64 PEs in all, one launch per
-    # iteration beyond
-    for F, M, want in ((1, 4, True), (4, 16, True), (1, 65, False), (4, 64, False)):
+    # AUTO: one launch per iteration, whatever the size
+    for F, M, want in ((1, 4, False), (4, 16, False), (1, 65, False), (4, 64, False)):
         c = dict(BASE, n_filters=F, n_pe=M, n_per_pe=1024, width=128, height=128, mode=1,
                  lik_mode=0, seed=1)
         t = p.Tracker(dict(c, launch=0), np.zeros((F, 5), np.float32))
