@@ -63,12 +63,14 @@ enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the
 #define PF_MAX_PE 8192u
 #define PF_MAX_PER_PE 4096u
 #define PF_MAX_PATCH 15u
+#define PF_MAX_PARTICLES (1u << 29)   /* F M N_p: state indices are 32-bit (5 F M N_p < 2^32) */
 
 typedef struct pf_ctx pf_ctx;   /* opaque; created by pf_init, freed by pf_destroy */
 
 typedef struct {
     uint32_t struct_size;       /* = sizeof(pf_config); ABI check */
-    uint32_t n_filters;         /* F: independent filters (one tracked object each) */
+    uint32_t n_filters;         /* F: independent filters (one tracked object each);
+                                   F M <= 2^24 and F M N_p <= PF_MAX_PARTICLES */
     uint32_t n_pe;              /* M: PEs per filter, 1..PF_MAX_PE */
     uint32_t n_per_pe;          /* N_p: particles per PE, 1..PF_MAX_PER_PE */
     uint32_t width, height;     /* frame size in pixels (patch mode) */

@@ -20,6 +20,7 @@ PF_LIK_PATCH, PF_LIK_POINT, PF_LIK_POISSON = 0, 1, 2
 PF_LAUNCH_AUTO, PF_LAUNCH_STEPWISE, PF_LAUNCH_PERSISTENT = 0, 1, 2
 PF_DEBUG_TRACE, PF_DEBUG_LINEAGE = 1, 2
 PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 4096, 15
+PF_MAX_PARTICLES = 1 << 29
 
 DBG = dict(state=0, logmass=1, pe_records=2, ring=3, nex=4, src=5, prop=6, ell=7, q=8,
            ancestors=9, v=10, lam=11, lineage=12)

@@ -286,7 +286,7 @@ int validate(const pf_config *c) {
     if (!(c->psf_sigma > 0.f) || !(c->noise_sigma > 0.f) || c->q < 0.f || c->sigma_I < 0.f)
         return PF_EINVAL;
     const uint64_t N = (uint64_t)c->n_filters * c->n_pe * c->n_per_pe;
-    if (N > (1ull << 31) || (uint64_t)c->n_filters * c->n_pe > (1ull << 24))
+    if (N > PF_MAX_PARTICLES || (uint64_t)c->n_filters * c->n_pe > (1ull << 24))
         return PF_EUNSUPPORTED;
     return PF_OK;
 }

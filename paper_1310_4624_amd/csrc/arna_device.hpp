@@ -396,25 +396,37 @@ __device__ __forceinline__ float wave_max_f32(float v) {
     });
     return __uint_as_float(lane63(r));
 }
-// Sum of a double over the wave (every lane gets it), in a fixed order.
-__device__ __forceinline__ double wave_total_f64(double v) {
-#define ARNA_DPP_F64(CTRL, ROWS)                                                      \
-    {                                                                                \
-        const uint64_t b = __double_as_longlong(v);                                  \
-        const uint32_t lo = dpp<CTRL, ROWS>((uint32_t)b, 0u);                         \
-        const uint32_t hi = dpp<CTRL, ROWS>((uint32_t)(b >> 32), 0u);                 \
-        v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));           \
+// Totals of six doubles over the wave by recursive halving: at each of the
+// steps across lane bits 5, 4 and 3 a lane keeps one half of its values and
+// adds the partner's copy of that half, so the work halves with the step;
+// bits 2..0 then sum the one value left.  Lane l ends with the total of
+// v[l >> 3] (l < 48), summed in a fixed order.
+__device__ __forceinline__ double wave_total6_f64(const double (&v)[6], const uint32_t lane) {
+    double a4[4];
+    {
+        const bool hi = lane & 32u;
+        const double x[8] = {v[0], v[1], v[2], v[3], v[4], v[5], 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double keep = hi ? x[i + 4] : x[i], send = hi ? x[i] : x[i + 4];
+            a4[i] = keep + __shfl_xor(send, 32, kWave);
+        }
     }
-    ARNA_DPP_F64(0x111, 0xF)
-    ARNA_DPP_F64(0x112, 0xF)
-    ARNA_DPP_F64(0x114, 0xF)
-    ARNA_DPP_F64(0x118, 0xF)
-    ARNA_DPP_F64(0x142, 0xA)
-    ARNA_DPP_F64(0x143, 0xC)
-#undef ARNA_DPP_F64
-    const uint64_t b = __double_as_longlong(v);
-    const uint32_t lo = lane63((uint32_t)b), hi = lane63((uint32_t)(b >> 32));
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    double a2[2];
+    {
+        const bool hi = lane & 16u;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double keep = hi ? a4[i + 2] : a4[i], send = hi ? a4[i] : a4[i + 2];
+            a2[i] = keep + __shfl_xor(send, 16, kWave);
+        }
+    }
+    const bool hi = lane & 8u;
+    double t = (hi ? a2[1] : a2[0]) + __shfl_xor(hi ? a2[0] : a2[1], 8, kWave);
+    t += __shfl_xor(t, 4, kWave);
+    t += __shfl_xor(t, 2, kWave);
+    t += __shfl_xor(t, 1, kWave);
+    return t;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -62,7 +62,7 @@ struct StepArgs {
     const DebugBufs *dbg;               // NULL unless a debug mode is on
     Lik lik;
     Dyn dyn;
-    uint32_t N;                         // F M N_p (< 2^31)
+    uint32_t N;                         // F M N_p (<= 2^29, so 5 N fits 32 bits)
     uint32_t M, np;
     uint32_t k, key0, key1;
     uint32_t mode, first, fixed_nex, initial_nex, cutoff_ppm, qmax;
@@ -696,11 +696,9 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const uint32_t bid,
         const uint32_t s = tid + q * B;
         if (s < np) mark[s] = 0;
     }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sums[c] = wave_total_f64(sums[c]);
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L.wsum[wave * 6 + c] = sums[c];
+    {
+        const double t = wave_total6_f64(sums, lane);
+        if ((lane & 7u) == 0 && lane < 48) L.wsum[wave * 6 + (lane >> 3)] = t;
     }
     __syncthreads();   // barrier 3: wave totals, marks cleared
     const uint32_t T = scan_finish<PPT>(cinc, L.wq, tid);

@@ -86,6 +86,19 @@ WORKLOADS = {
                  speed=(0.5, 1.0), start_box=(160.0, 352.0), margin=16.0, min_sep=24.0,
                  q_true=0.001, noise="poisson"),
     ),
+    # The tracking workload scaled to 2^24 particles: 64 spots of SNR 2..6
+    # (one filter each) x 64 PEs x 4096, 512^2, 40 frames.  Its state (2 x 320
+    # MiB ping-pong) does not fit the 256 MB Infinity Cache.
+    "arna_tracking_512_64x64x4096": dict(
+        filter=dict(n_filters=64, n_pe=64, n_per_pe=4096, width=512, height=512, patch=9,
+                    mode=MODE_ARNA, init_mode=INIT_TRACKING, lik_mode=LIK_PATCH,
+                    fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
+                    psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5),
+        seq=dict(width=512, height=512, frames=40,
+                 intensities=[2.0 * s for s in np.linspace(2.0, 6.0, 64)], motion="ncv",
+                 speed=(0.5, 1.0), start_box=(48.0, 464.0), margin=16.0, min_sep=24.0,
+                 q_true=0.001, windowed=True),
+    ),
     # Differentiable run: the information-sharing shape (256 PEs x 4096, 512^2,
     # one spot of SNR 4) over 50 frames, every particle starting at the truth,
     # so that the intensity gradient is the one of the true initial intensity.
@@ -196,8 +209,9 @@ def make_sequence(workload: str, seed: int = 1000, frames: int | None = None) ->
             out[k - 1] = render_poisson(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
                                         fl["background"], rng)
         else:
-            out[k - 1] = render(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
-                                fl["background"], fl["noise_sigma"], rng)
+            draw = render_windowed if sq.get("windowed") else render
+            out[k - 1] = draw(truth[k], sq["width"], sq["height"], fl["psf_sigma"],
+                              fl["background"], fl["noise_sigma"], rng)
     return Sequence(frames=out, truth=truth, spots=len(sq["intensities"]))
 
 

@@ -88,6 +88,8 @@ def _init(L, **kw):
     (dict(n_filters=0), nat.PF_EINVAL),
     (dict(n_pe=nat.PF_MAX_PE + 1), nat.PF_EUNSUPPORTED),
     (dict(n_per_pe=nat.PF_MAX_PER_PE + 1), nat.PF_EUNSUPPORTED),
+    # 17 x 8192 x 4096 > 2^29 particles: 32-bit state indices would wrap
+    (dict(n_filters=17, n_pe=nat.PF_MAX_PE, n_per_pe=nat.PF_MAX_PER_PE), nat.PF_EUNSUPPORTED),
     (dict(patch=8), nat.PF_EINVAL),
     (dict(patch=17), nat.PF_EUNSUPPORTED),
     (dict(mode=2), nat.PF_EINVAL),
@@ -151,3 +153,12 @@ def test_build_flags_target_gfx950_without_packed_fp32():
     assert "-disable-machine-licm" in cmds[1] and "-disable-machine-licm" not in cmds[0]
     assert cmds[0][-1].endswith("arna.hip") and cmds[1][-1].endswith("arna_run.hip")
     assert "-shared" in cmds[2]
+
+def test_limit_constants_match_header():
+    """The binding's size limits are the header's #defines."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"#define\s+(PF_MAX_\w+)\s+(.+)", text))
+    assert set(defs) == {"PF_MAX_PE", "PF_MAX_PER_PE", "PF_MAX_PATCH", "PF_MAX_PARTICLES"}
+    for name, expr in defs.items():
+        val = eval(re.sub(r"(\d+)u\b", r"\1", expr.strip()), {})
+        assert getattr(nat, name) == val, name
