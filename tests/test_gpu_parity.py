@@ -500,7 +500,7 @@ def test_gpu_random_ring_infection_at_most_doubles():
 # ---------------------------------------------- Philox against rocRAND (P8)
 def test_oracle_philox_matches_rocrand_host_generator():
     """rocRAND's PHILOX4_32_10 run as a black box (its host generator needs a
-    HIP device to allocate, so this runs on the GPU machine)."""
+    HIP device to allocate, so this test needs a GPU)."""
     import os
     path = "/opt/rocm/lib/librocrand.so"
     lib = ctypes.CDLL(path if os.path.exists(path) else "librocrand.so")
