@@ -333,16 +333,16 @@ static particle propagate(particle p, const double eps[5], double q, double sigm
  * Point mode: z is an observed position, l = -|(x, y) - z|^2 / (2 sigma_n^2).
  * Poisson mode: every pixel is a photon count z ~ Poisson(B + I g) (the noise
  * of the paper's synthetic images, Fig. 1); against the background-only
- * model, log p(z | B + I g) - log p(z | B) = z log(1 + I g / B) - I g. */
-static double log_likelihood(const orc_config *c, const float *frame, uint32_t f, particle p)
+ * model, log p(z | B + I g) - log p(z | B) = z log(1 + I g / B) - I g.
+ *
+ * The patch centre is the nearest pixel, floor(x + 1/2) per axis; the sum
+ * itself is loglik_at_centre.  A centre more than half a patch outside the
+ * image gives l = 0 (no pixel of the patch is in the image). */
+static double loglik_at_centre(const orc_config *c, const float *frame, particle p,
+                               double fx, double fy)
 {
     double s2 = c->noise_sigma * c->noise_sigma;
-    if (c->lik_mode == ORC_LIK_POINT) {
-        double dx = p.x - (double)frame[2 * f], dy = p.y - (double)frame[2 * f + 1];
-        return -(dx * dx + dy * dy) / (2.0 * s2);
-    }
     int half = (int)c->patch / 2;
-    double fx = floor(p.x + 0.5), fy = floor(p.y + 0.5);
     if (!(fx >= -half && fx <= (double)c->width - 1 + half)) return 0.0;
     if (!(fy >= -half && fy <= (double)c->height - 1 + half)) return 0.0;
     long cx = (long)fx, cy = (long)fy;
@@ -366,6 +366,31 @@ static double log_likelihood(const orc_config *c, const float *frame, uint32_t f
     return l;
 }
 
+static double log_likelihood(const orc_config *c, const float *frame, uint32_t f, particle p)
+{
+    if (c->lik_mode == ORC_LIK_POINT) {
+        double s2 = c->noise_sigma * c->noise_sigma;
+        double dx = p.x - (double)frame[2 * f], dy = p.y - (double)frame[2 * f + 1];
+        return -(dx * dx + dy * dy) / (2.0 * s2);
+    }
+    return loglik_at_centre(c, frame, p, floor(p.x + 0.5), floor(p.y + 0.5));
+}
+
+/* The nearest-pixel decision floor(x + 1/2) of a coordinate computed with a
+ * rounding error of at most eps may land on either side of a pixel boundary
+ * (x + 1/2 an integer) when x lies within eps of it: both centres are then
+ * valid outcomes of the decision.  Returns 1 and the other centre in *alt
+ * when that is the case. */
+static int centre_ambiguous(double x, double eps_rel, double eps_abs, double *alt)
+{
+    double t = x + 0.5, b = floor(t + 0.5);
+    double eps = eps_rel * (fabs(x) > 1.0 ? fabs(x) : 1.0) + eps_abs;
+    if (!(fabs(t - b) <= eps)) return 0;
+    double c0 = floor(t);
+    *alt = (c0 == b) ? b - 1.0 : b;
+    return 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The filter object: particles, per-PE log weights, iteration counter.      */
 /* ------------------------------------------------------------------------ */
@@ -375,6 +400,8 @@ typedef struct {
     particle *s;          /* [N] resampled particles of iteration k */
     double *L;            /* [F*M] log W^(m)_k (0 before the first iteration) */
     int *lineage;         /* [N] optional tag: PE a particle's lineage started on */
+    double amb_rel, amb_abs;  /* > 0: record the alternative patch centres (see
+                                 orc_set_ambiguity) */
 } orc_filter;
 
 /* Per-iteration outputs; every pointer may be NULL. */
@@ -402,6 +429,9 @@ typedef struct {
     double *log_z;        /* [F] log p(z_k | z_1:k-1) (ratio form) */
     uint32_t *n_ex_next;  /* [F] what step 2 of the next iteration will use */
     int32_t *lineage;     /* [N] lineage tag after resampling */
+    uint32_t *amb;        /* [N] bit 0 / bit 1: the x / y patch centre is ambiguous */
+    double *ell_alt;      /* [N][3] l with the other x centre, other y centre, both
+                             (NaN where that alternative does not exist) */
 } orc_trace;
 
 static size_t n_total(const orc_config *c) { return (size_t)c->n_filters * c->n_pe * c->n_per_pe; }
@@ -521,6 +551,108 @@ static void pe_masses(const double *L, uint32_t M, uint32_t *P)
         P[m] = (mx == -INFINITY) ? 0u : (uint32_t)floor(exp(L[m] - mx) * 1048576.0);
 }
 
+/* Steps 6-7 of Alg. 3 for one PE (filter f, PE m, iteration k): from the
+ * carried log-weights lam[i] (step 4) and log-likelihoods ell[i] (step 5) of
+ * its n_p particles prop[i], the local estimate x^m (6), the log weight sum
+ * L = log W^(m) and its maximum term lstar, and local systematic resampling
+ * (7) on the fixed-point weights Q_i = floor(w_i Q_max), w_i = e^{lam+ell-lstar}:
+ * total T, offset V and ancestors anc[j].  Returns 0, or -4 when the weights
+ * are unusable (NaN, or all zero): the ancestors are then the identity. */
+int orc_pe_update(const orc_config *c, uint32_t f, uint32_t k, uint32_t m, uint32_t np,
+                  const double *lam, const double *ell, const double *prop /* [5][np] */,
+                  double xm[5], double *L_out, double *lstar_out, uint32_t *Q, uint32_t *T_out,
+                  uint32_t *V_out, uint32_t *anc)
+{
+    int status = 0;
+    const uint32_t qmax = orc_qmax(np);
+    /* 6: local estimate and local weight sum, with the max subtracted. */
+    double lstar = -INFINITY;
+    for (uint32_t s = 0; s < np; ++s) {
+        double u = lam[s] + ell[s];
+        if (u > lstar) lstar = u;
+    }
+    double *w = (double *)malloc(sizeof(double) * np);
+    double wsum = 0.0;
+    for (uint32_t s = 0; s < np; ++s) {
+        w[s] = (lstar == -INFINITY) ? 1.0 : exp(lam[s] + ell[s] - lstar);
+        wsum += w[s];
+    }
+    for (int d = 0; d < 5; ++d) {
+        double acc = 0.0;
+        for (uint32_t s = 0; s < np; ++s) acc += w[s] * prop[(size_t)d * np + s];
+        xm[d] = acc / wsum;
+    }
+    *L_out = (lstar == -INFINITY) ? -INFINITY : lstar + log(wsum);
+    *lstar_out = lstar;
+
+    /* 7: systematic resampling with the locally normalized weights,
+     * represented as Q_i = floor(w_i Q_max). */
+    uint64_t T = 0;
+    for (uint32_t s = 0; s < np; ++s) {
+        double qd = floor(w[s] * (double)qmax);
+        if (!(qd >= 0.0)) qd = 0.0;          /* NaN guard */
+        if (qd > (double)qmax) qd = (double)qmax;
+        Q[s] = (uint32_t)qd;
+        T += Q[s];
+    }
+    uint32_t V = 0;
+    if (T > 0 && T <= 0xFFFFFFFFull) {
+        V = orc_resample_offset(c->seed, f, k, m, (uint32_t)T);
+        orc_resample(Q, np, V, anc);
+    } else {
+        for (uint32_t s = 0; s < np; ++s) anc[s] = s;
+        status = -4;
+    }
+    for (uint32_t s = 0; s < np; ++s)
+        if (isnan(ell[s])) status = -4;
+    *T_out = (uint32_t)T;
+    *V_out = V;
+    free(w);
+    return status;
+}
+
+/* Steps 9-10 of Alg. 3 for one filter: from the M PE log masses L[m] =
+ * log W^(m)_k and estimates xm[m][5], the master's W_k (as L_glob), the
+ * global estimate x_k = sum_m W^(m) x^m / W_k, the integer PE masses
+ * P_m = floor(e^{L_m - max L} 2^20) behind Eq. 4, PE_eff = S^2 / D, the
+ * likelihood increment log p(z_k | z_1..z_{k-1}) = L_glob - log N_p (the
+ * carried weights of the step sum to N_p), and the N_ex of Eq. 3 for the
+ * next iteration.  Every output pointer may be NULL. */
+void orc_master(const orc_config *c, const double *L, const double *xm, double *L_glob,
+                double xhat[5], uint32_t *P_out, double *pe_eff, double *log_z,
+                uint32_t *nex_next)
+{
+    const uint32_t M = c->n_pe, np = c->n_per_pe;
+    double Lg = logsumexp(L, M);
+    uint32_t *P = (uint32_t *)malloc(sizeof(uint32_t) * M);
+    pe_masses(L, M, P);
+    double S = 0.0, D = 0.0;
+    for (uint32_t m = 0; m < M; ++m) { S += (double)P[m]; D += (double)P[m] * (double)P[m]; }
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (uint32_t m = 0; m < M; ++m) {
+        if (L[m] == -INFINITY) continue;
+        double wm = exp(L[m] - Lg);
+        for (int d = 0; d < 5; ++d) acc[d] += wm * xm[(size_t)m * 5 + d];
+    }
+    if (L_glob) *L_glob = Lg;
+    if (P_out) memcpy(P_out, P, sizeof(uint32_t) * M);
+    if (pe_eff) *pe_eff = D > 0 ? S * S / D : 0.0;
+    if (log_z) *log_z = Lg - log((double)np);
+    if (nex_next)
+        *nex_next = orc_nex(P, M, np, c->mode, c->fixed_ratio, c->initial_ratio, c->eff_cutoff, 0);
+    if (xhat) for (int d = 0; d < 5; ++d) xhat[d] = acc[d];
+    free(P);
+}
+
+/* Record, from the next orc_step on, which patch centres are ambiguous for a
+ * coordinate error of eps_rel * max(|x|, 1) + eps_abs, and the likelihoods at
+ * the other centres (trace fields amb, ell_alt).  Zero turns it off. */
+void orc_set_ambiguity(orc_filter *o, double eps_rel, double eps_abs)
+{
+    o->amb_rel = eps_rel;
+    o->amb_abs = eps_abs;
+}
+
 /* One iteration k = o->k + 1 of Alg. 3 (ARNA) or Alg. 2 (RNA) on every filter.
  * frame: patch mode [H][W] row-major; point mode [F][2]. */
 int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
@@ -529,7 +661,6 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
     const uint32_t F = c->n_filters, M = c->n_pe, np = c->n_per_pe;
     const size_t N = n_total(c);
     const uint32_t k = o->k + 1;
-    const uint32_t qmax = orc_qmax(np);
     int status = 0;
 
     particle *src_particles = (particle *)malloc(sizeof(particle) * N);
@@ -600,6 +731,7 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
     }
 
     /* 5-8 on every PE independently. */
+    const int amb_on = (o->amb_rel > 0.0 || o->amb_abs > 0.0) && c->lik_mode != ORC_LIK_POINT;
     #pragma omp parallel for schedule(static)
     for (long fm = 0; fm < (long)F * M; ++fm) {
         uint32_t f = (uint32_t)(fm / M), m = (uint32_t)(fm % M);
@@ -614,57 +746,40 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
             five_normals(r, eps);
             prop[g] = propagate(src_particles[g], eps, c->q, c->sigma_I);
             ell[g] = log_likelihood(c, frame, f, prop[g]);
-        }
-
-        /* 6: local estimate and local weight sum, with the max subtracted. */
-        double lstar = -INFINITY;
-        for (uint32_t s = 0; s < np; ++s) {
-            double u = lam[base + s] + ell[base + s];
-            if (u > lstar) lstar = u;
-        }
-        double *w = (double *)malloc(sizeof(double) * np);
-        double wsum = 0.0;
-        for (uint32_t s = 0; s < np; ++s) {
-            w[s] = (lstar == -INFINITY) ? 1.0 : exp(lam[base + s] + ell[base + s] - lstar);
-            wsum += w[s];
-        }
-        double xm[5] = {0, 0, 0, 0, 0};
-        for (uint32_t s = 0; s < np; ++s) {
-            const particle *p = &prop[base + s];
-            xm[0] += w[s] * p->x; xm[1] += w[s] * p->y;
-            xm[2] += w[s] * p->vx; xm[3] += w[s] * p->vy; xm[4] += w[s] * p->I;
-        }
-        for (int d = 0; d < 5; ++d) xm[d] /= wsum;
-        for (int d = 0; d < 5; ++d) xm_all[(size_t)fm * 5 + d] = xm[d];
-        double Lm = (lstar == -INFINITY) ? -INFINITY : lstar + log(wsum);
-
-        /* 7: systematic resampling with the locally normalized weights,
-         * represented as Q_i = floor(w_i Q_max). */
-        uint32_t *Q = (uint32_t *)malloc(sizeof(uint32_t) * np);
-        uint32_t *anc = (uint32_t *)malloc(sizeof(uint32_t) * np);
-        uint64_t T = 0;
-        for (uint32_t s = 0; s < np; ++s) {
-            double qd = floor(w[s] * (double)qmax);
-            if (!(qd >= 0.0)) qd = 0.0;          /* NaN guard */
-            if (qd > (double)qmax) qd = (double)qmax;
-            Q[s] = (uint32_t)qd;
-            T += Q[s];
-        }
-        uint32_t V = 0;
-        if (T > 0 && T <= 0xFFFFFFFFull) {
-            V = orc_resample_offset(c->seed, f, k, m, (uint32_t)T);
-            orc_resample(Q, np, V, anc);
-        } else {
-            for (uint32_t s = 0; s < np; ++s) anc[s] = s;
-            #pragma omp atomic write
-            status = -4;
-        }
-        for (uint32_t s = 0; s < np; ++s) {
-            if (isnan(ell[base + s])) {
-                #pragma omp atomic write
-                status = -4;
+            if (amb_on && tr && (tr->amb || tr->ell_alt)) {
+                const particle p = prop[g];
+                double ax = 0.0, ay = 0.0;
+                uint32_t bits = (uint32_t)centre_ambiguous(p.x, o->amb_rel, o->amb_abs, &ax) |
+                                ((uint32_t)centre_ambiguous(p.y, o->amb_rel, o->amb_abs, &ay) << 1);
+                if (tr->amb) tr->amb[g] = bits;
+                if (tr->ell_alt) {
+                    const double fx = floor(p.x + 0.5), fy = floor(p.y + 0.5);
+                    tr->ell_alt[3 * g + 0] = (bits & 1u) ? loglik_at_centre(c, frame, p, ax, fy) : NAN;
+                    tr->ell_alt[3 * g + 1] = (bits & 2u) ? loglik_at_centre(c, frame, p, fx, ay) : NAN;
+                    tr->ell_alt[3 * g + 2] = (bits == 3u) ? loglik_at_centre(c, frame, p, ax, ay) : NAN;
+                }
             }
         }
+
+        /* 6-7: local estimate, weight sum and systematic resampling. */
+        double *pc = (double *)malloc(sizeof(double) * 5 * np);
+        for (uint32_t s = 0; s < np; ++s) {
+            const particle *p = &prop[base + s];
+            pc[0 * (size_t)np + s] = p->x; pc[1 * (size_t)np + s] = p->y;
+            pc[2 * (size_t)np + s] = p->vx; pc[3 * (size_t)np + s] = p->vy;
+            pc[4 * (size_t)np + s] = p->I;
+        }
+        uint32_t *Q = (uint32_t *)malloc(sizeof(uint32_t) * np);
+        uint32_t *anc = (uint32_t *)malloc(sizeof(uint32_t) * np);
+        double xm[5], Lm, lstar;
+        uint32_t T, V;
+        int st = orc_pe_update(c, f, k, m, np, lam + base, ell + base, pc, xm, &Lm, &lstar, Q, &T,
+                               &V, anc);
+        if (st != 0) {
+            #pragma omp atomic write
+            status = st;
+        }
+        for (int d = 0; d < 5; ++d) xm_all[(size_t)fm * 5 + d] = xm[d];
         /* 8: every resampled particle of PE m carries W^(m)_k. */
         for (uint32_t j = 0; j < np; ++j) {
             o->s[base + j] = prop[base + anc[j]];
@@ -675,41 +790,23 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
         if (tr) {
             if (tr->Q) memcpy(tr->Q + base, Q, sizeof(uint32_t) * np);
             if (tr->anc) memcpy(tr->anc + base, anc, sizeof(uint32_t) * np);
-            if (tr->T) tr->T[fm] = (uint32_t)T;
+            if (tr->T) tr->T[fm] = T;
             if (tr->V) tr->V[fm] = V;
             if (tr->L_pe) tr->L_pe[fm] = Lm;
             if (tr->lstar) tr->lstar[fm] = lstar;
             if (tr->xhat_pe) for (int d = 0; d < 5; ++d) tr->xhat_pe[fm * 5 + d] = xm[d];
         }
-        free(Q); free(anc); free(w);
+        free(Q); free(anc); free(pc);
     }
 
     /* 9-10: master: W_k = sum_m W^(m)_k, the global estimate
      * x_k = sum_m W^(m)_k x^m_k / W_k, and the PE masses behind Eq. 4. */
     for (uint32_t f = 0; f < F; ++f) {
-        const double *Lf = Lnew + (size_t)f * M;
-        double Lg = logsumexp(Lf, M);
-        uint32_t *P = (uint32_t *)malloc(sizeof(uint32_t) * M);
-        pe_masses(Lf, M, P);
-        double S = 0.0, D = 0.0;
-        for (uint32_t m = 0; m < M; ++m) { S += (double)P[m]; D += (double)P[m] * (double)P[m]; }
-        double acc[5] = {0, 0, 0, 0, 0};
-        for (uint32_t m = 0; m < M; ++m) {
-            if (Lf[m] == -INFINITY) continue;
-            double wm = exp(Lf[m] - Lg);
-            for (int d = 0; d < 5; ++d) acc[d] += wm * xm_all[((size_t)f * M + m) * 5 + d];
-        }
-        if (tr) {
-            if (tr->L_glob) tr->L_glob[f] = Lg;
-            if (tr->P) memcpy(tr->P + (size_t)f * M, P, sizeof(uint32_t) * M);
-            if (tr->pe_eff) tr->pe_eff[f] = D > 0 ? S * S / D : 0.0;
-            if (tr->log_z) tr->log_z[f] = Lg - log((double)np);
-            if (tr->n_ex_next)
-                tr->n_ex_next[f] = orc_nex(P, M, np, c->mode, c->fixed_ratio, c->initial_ratio,
-                                           c->eff_cutoff, 0);
-            if (tr->xhat) for (int d = 0; d < 5; ++d) tr->xhat[5 * f + d] = acc[d];
-        }
-        free(P);
+        if (!tr) continue;
+        orc_master(c, Lnew + (size_t)f * M, xm_all + (size_t)f * M * 5,
+                   tr->L_glob ? tr->L_glob + f : NULL, tr->xhat ? tr->xhat + 5 * f : NULL,
+                   tr->P ? tr->P + (size_t)f * M : NULL, tr->pe_eff ? tr->pe_eff + f : NULL,
+                   tr->log_z ? tr->log_z + f : NULL, tr->n_ex_next ? tr->n_ex_next + f : NULL);
     }
 
     if (tr) {

@@ -75,6 +75,7 @@ _TRACE_FIELDS = [
     ("L_glob", ctypes.c_double, "F"), ("P", ctypes.c_uint32, "FM"),
     ("pe_eff", ctypes.c_double, "F"), ("log_z", ctypes.c_double, "F"),
     ("n_ex_next", ctypes.c_uint32, "F"), ("lineage", ctypes.c_int32, "N"),
+    ("amb", ctypes.c_uint32, "N"), ("ell_alt", ctypes.c_double, "N3"),
 ]
 
 
@@ -127,6 +128,11 @@ def _declare(L):
     L.orc_replay.argtypes = [ctypes.POINTER(_Config), PD, ctypes.c_double, PF, u32, P32, P32,
                              PI32, PD]
     L.orc_replay.restype = i32
+    L.orc_set_ambiguity.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    L.orc_pe_update.argtypes = [ctypes.POINTER(_Config), u32, u32, u32, u32, PD, PD, PD, PD, PD,
+                                PD, P32, P32, P32, P32]
+    L.orc_pe_update.restype = i32
+    L.orc_master.argtypes = [ctypes.POINTER(_Config), PD, PD, PD, PD, P32, PD, PD, P32]
 
 
 def _p(a, ct):
@@ -304,6 +310,12 @@ class Oracle:
             Lp = _p(Larr, ctypes.c_double)
         lib().orc_set_state(self._h, _p(s, ctypes.c_double), Lp, k)
 
+    def set_ambiguity(self, eps_rel: float, eps_abs: float):
+        """From the next step on, trace which patch centres a coordinate error
+        of eps_rel * max(|x|, 1) + eps_abs could move (``amb``) and the
+        likelihoods at the other centres (``ell_alt``); 0, 0 turns it off."""
+        lib().orc_set_ambiguity(self._h, float(eps_rel), float(eps_abs))
+
     def set_lineage(self, tag):
         t = np.ascontiguousarray(np.asarray(tag, dtype=np.int32).reshape(-1))
         lib().orc_set_lineage(self._h, _p(t, ctypes.c_int32))
@@ -325,7 +337,7 @@ class Oracle:
         F, M, N = c.n_filters, c.n_pe, c.N
         fr = np.ascontiguousarray(np.asarray(frame, dtype=np.float32))
         shapes = {"F": (F,), "FM": (F, M), "N": (N,), "5N": (5, N), "FM5": (F, M, 5),
-                  "F5": (F, 5)}
+                  "F5": (F, 5), "N3": (N, 3)}
         dt = {ctypes.c_uint32: np.uint32, ctypes.c_int64: np.int64, ctypes.c_double: np.float64,
               ctypes.c_int32: np.int32}
         tr = _Trace()
@@ -340,6 +352,53 @@ class Oracle:
         rc = lib().orc_step(self._h, _p(fr, ctypes.c_float), ctypes.byref(tr) if trace else None)
         out["status"] = int(rc)
         return out
+
+
+def pe_update(cfg, f: int, k: int, m: int, lam, ell, prop) -> dict:
+    """Steps 6-7 of one PE from its carried log-weights, log-likelihoods and
+    propagated particles ([5][n_p]), exactly as ``Oracle.step`` runs them."""
+    if isinstance(cfg, dict):
+        cfg = OracleConfig.from_dict(cfg)
+    c = cfg.to_c()
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    ell = np.ascontiguousarray(ell, dtype=np.float64)
+    prop = np.ascontiguousarray(prop, dtype=np.float64)
+    n_p = len(lam)
+    xm = np.zeros(5)
+    L = np.zeros(1)
+    lstar = np.zeros(1)
+    Q = np.zeros(n_p, np.uint32)
+    T = np.zeros(1, np.uint32)
+    V = np.zeros(1, np.uint32)
+    anc = np.zeros(n_p, np.uint32)
+    PD = ctypes.c_double
+    st = lib().orc_pe_update(ctypes.byref(c), f, k, m, n_p, _p(lam, PD), _p(ell, PD),
+                             _p(prop, PD), _p(xm, PD), _p(L, PD), _p(lstar, PD),
+                             _p(Q, ctypes.c_uint32), _p(T, ctypes.c_uint32),
+                             _p(V, ctypes.c_uint32), _p(anc, ctypes.c_uint32))
+    return {"xhat_pe": xm, "L_pe": float(L[0]), "lstar": float(lstar[0]), "Q": Q,
+            "T": int(T[0]), "V": int(V[0]), "anc": anc, "status": int(st)}
+
+
+def master(cfg, L_pe, xhat_pe) -> dict:
+    """Steps 9-10 of one filter from its PE log masses [M] and estimates [M][5]."""
+    if isinstance(cfg, dict):
+        cfg = OracleConfig.from_dict(cfg)
+    c = cfg.to_c()
+    M = cfg.n_pe
+    L = np.ascontiguousarray(L_pe, dtype=np.float64)
+    xm = np.ascontiguousarray(xhat_pe, dtype=np.float64)
+    Lg = np.zeros(1)
+    xh = np.zeros(5)
+    P = np.zeros(M, np.uint32)
+    eff = np.zeros(1)
+    lz = np.zeros(1)
+    nx = np.zeros(1, np.uint32)
+    PD = ctypes.c_double
+    lib().orc_master(ctypes.byref(c), _p(L, PD), _p(xm, PD), _p(Lg, PD), _p(xh, PD),
+                     _p(P, ctypes.c_uint32), _p(eff, PD), _p(lz, PD), _p(nx, ctypes.c_uint32))
+    return {"L_glob": float(Lg[0]), "xhat": xh, "P": P, "pe_eff": float(eff[0]),
+            "log_z": float(lz[0]), "n_ex_next": int(nx[0])}
 
 
 # ------------------------------------------------------------------ gradient

@@ -12,7 +12,10 @@ in the oracle) started from the same float32 inputs:
     Q_max w (du + dlstar) + 2.
 Particles whose oracle position lies within the coordinate tolerance of a
 pixel boundary (x + 1/2 an integer) may sit on different patches on the two
-sides; they are not compared element-wise (they are counted and must be rare).
+sides: both patch centres are valid outcomes of the nearest-pixel decision.
+The oracle reports the likelihood at the other centre(s) for such particles;
+the comparison takes the one the GPU value agrees with, and the oracle
+recomputes the per-PE and master steps for that choice (``select_branches``).
 """
 from __future__ import annotations
 
@@ -35,16 +38,25 @@ def patch_flip_mask(x, y, tol_x, tol_y):
     return (fx < tol_x) | (fx > 1 - tol_x) | (fy < tol_y) | (fy > 1 - tol_y)
 
 
-def ell_tolerance(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I):
-    """Per-particle bound on |l_gpu - l_oracle| for patch mode (prop: [5][n])."""
+# The rounding a coordinate may carry on the GPU side (coord_tol) plus the
+# float32 rounding of x + 1/2 in the nearest-pixel decision, as the ambiguity
+# window of the oracle: eps_rel max(|x|, 1) + eps_abs.
+AMB_EPS_REL = 4.0 * 2.0 ** -23
+AMB_EPS_ABS = 2e-5
+
+
+def ell_tolerance(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I,
+                  cx=None, cy=None):
+    """Per-particle bound on |l_gpu - l_oracle| for patch mode (prop: [5][n]),
+    with the patch centred at (cx, cy) (default: the nearest pixel)."""
     x, y, I = prop[0], prop[1], prop[4]
     half = cfg["patch"] // 2
     H, W = frame.shape
     s2 = cfg["psf_sigma"] ** 2
     sn2 = cfg["noise_sigma"] ** 2
     B = cfg["background"]
-    cx = np.floor(x + 0.5)
-    cy = np.floor(y + 0.5)
+    cx = np.floor(x + 0.5) if cx is None else np.asarray(cx, np.float64)
+    cy = np.floor(y + 0.5) if cy is None else np.asarray(cy, np.float64)
     gx_abs_sum = np.zeros_like(x)
     gy_abs_sum = np.zeros_like(x)
     ggx = np.zeros_like(x)
@@ -83,7 +95,8 @@ def ell_tolerance(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, 
     return 1.25 * (Gx * tol_x + Gy * tol_y + GI * tol_I) + 2e-6 * mag + 1e-6
 
 
-def ell_tolerance_poisson(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I):
+def ell_tolerance_poisson(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x, tol_y, tol_I,
+                          cx=None, cy=None):
     """Per-particle bound on |l_gpu - l_oracle| for Poisson patch mode,
     l = sum [z log(1 + I g / B) - I g]: the gradient of l times the coordinate
     tolerances, plus FP32 rounding (the float log of 1 + t/B carries an
@@ -93,8 +106,8 @@ def ell_tolerance_poisson(cfg: dict, frame: np.ndarray, prop: np.ndarray, tol_x,
     H, W = frame.shape
     s2 = cfg["psf_sigma"] ** 2
     B = cfg["background"]
-    cx = np.floor(x + 0.5)
-    cy = np.floor(y + 0.5)
+    cx = np.floor(x + 0.5) if cx is None else np.asarray(cx, np.float64)
+    cy = np.floor(y + 0.5) if cy is None else np.asarray(cy, np.float64)
     ok = np.isfinite(cx) & np.isfinite(cy) & (np.abs(cx) < 1e8) & (np.abs(cy) < 1e8)
     cxi = np.where(ok, cx, -10 ** 6).astype(np.int64)
     cyi = np.where(ok, cy, -10 ** 6).astype(np.int64)
@@ -146,3 +159,64 @@ def check_ancestors(Qg, Vg, ancg, Qo, Vo, anco, tolQ):
         d = np.min(np.abs(rho[j] - beta[a:b]))
         assert d <= eps, (j, int(ancg[j]), int(anco[j]), d, eps)
     return len(mism)
+
+
+def other_centre(x):
+    """The other nearest-pixel candidate of a coordinate next to a boundary."""
+    t = np.asarray(x) + 0.5
+    b = np.floor(t + 0.5)
+    c0 = np.floor(t)
+    return np.where(c0 == b, b - 1.0, b)
+
+
+def select_branches(cfg: dict, frame, tr: dict, ell_gpu, tol_fn, tol_xyI, k: int):
+    """Oracle reference values for the patch-centre choices the GPU made.
+
+    For every particle whose patch centre is ambiguous (oracle trace ``amb``),
+    the candidate likelihoods are the oracle's own at its centre and at the
+    other centre(s) (``ell_alt``); the candidate nearest the GPU value is
+    taken (any of them is a valid outcome).  For every PE with a particle on
+    another centre than the oracle's, the oracle reruns steps 6-7
+    (``orc_pe_update``) with those likelihoods, and the master step 9-10
+    (``orc_master``) of its filter is rerun.  Returns (ref, tl, chosen): ref
+    holds the trace arrays with those replacements, tl the per-particle
+    likelihood tolerance at the chosen centres, chosen the candidate index
+    (0: the oracle's centre, 1: other x, 2: other y, 3: both)."""
+    F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
+    prop = tr["prop"]
+    tol_x, tol_y, tol_I = tol_xyI
+    ref = {key: np.array(v, copy=True) for key, v in tr.items() if isinstance(v, np.ndarray)}
+    cand = np.concatenate([tr["ell"][:, None], tr["ell_alt"]], axis=1)
+    dist = np.abs(cand - np.asarray(ell_gpu, np.float64)[:, None])
+    dist[~np.isfinite(cand)] = np.inf
+    chosen = np.argmin(dist, axis=1)
+    ref["ell"] = cand[np.arange(len(chosen)), chosen]
+    cx = np.floor(prop[0] + 0.5)
+    cy = np.floor(prop[1] + 0.5)
+    cx = np.where((chosen == 1) | (chosen == 3), other_centre(prop[0]), cx)
+    cy = np.where((chosen == 2) | (chosen == 3), other_centre(prop[1]), cy)
+    tl = np.zeros(len(chosen))
+    for f in range(F):
+        sl = slice(f * M * n_p, (f + 1) * M * n_p)
+        tl[sl] = tol_fn(cfg, frame, prop[:, sl], tol_x[sl], tol_y[sl], tol_I[sl], cx[sl], cy[sl])
+    moved = chosen.reshape(F * M, n_p) != 0
+    for pe in np.flatnonzero(moved.any(axis=1)):
+        f, m = divmod(int(pe), M)
+        sl = slice(pe * n_p, (pe + 1) * n_p)
+        r = orc.pe_update(cfg, f, k, m, tr["lambda"][sl], ref["ell"][sl], prop[:, sl])
+        ref["Q"][sl] = r["Q"]
+        ref["anc"][sl] = r["anc"]
+        ref["T"][f, m] = r["T"]
+        ref["V"][f, m] = r["V"]
+        ref["L_pe"][f, m] = r["L_pe"]
+        ref["lstar"][f, m] = r["lstar"]
+        ref["xhat_pe"][f, m] = r["xhat_pe"]
+    for f in sorted({int(pe) // M for pe in np.flatnonzero(moved.any(axis=1))}):
+        g = orc.master(cfg, ref["L_pe"][f], ref["xhat_pe"][f])
+        ref["xhat"][f] = g["xhat"]
+        ref["L_glob"][f] = g["L_glob"]
+        ref["P"][f] = g["P"]
+        ref["pe_eff"][f] = g["pe_eff"]
+        ref["log_z"][f] = g["log_z"]
+        ref["n_ex_next"][f] = g["n_ex_next"]
+    return ref, tl, chosen
