@@ -138,6 +138,19 @@ typedef struct {
     uint64_t step;              /* k: iterations completed */
 } pf_estimate_t;
 
+/* The master step of one iteration for one filter (Alg. 3, steps 9-10): what
+ * the master computes from the PE records and broadcasts. */
+typedef struct {
+    double xhat[5];             /* x_k = sum_m W^(m)_k x^m_k / W_k */
+    double log_mass_glob;       /* log W_k = log sum_m W^(m)_k */
+    double pe_eff;              /* PE_eff of Eq. 4 on the integer PE masses
+                                   P_m = floor(exp(L_m - max L) 2^20), in [1, M]; 0 without mass */
+    double log_z_inc;           /* log p(z_k | z_1:k-1) in likelihood-ratio form: log W_k - log N_p */
+    uint32_t n_ex;              /* N_ex used in iteration k */
+    uint32_t n_ex_next;         /* N_ex iteration k+1 will use (Eq. 3; the fixed rules in RNA) */
+    uint64_t step;              /* k */
+} pf_master_t;
+
 /* Per-PE record, the message each PE sends to the master (Alg. 3, step 9). */
 typedef struct {
     double log_mass;            /* log W^(m)_k */
@@ -160,6 +173,16 @@ int pf_step(pf_ctx *c, const float *d_frame);
 /* n_steps iterations on consecutive frames d_frames + i * frame_stride
  * (stride in floats).  Same semantics as n_steps calls of pf_step. */
 int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride);
+
+/* pf_run that also writes the master step of every iteration (Alg. 3, steps
+ * 9-10: global estimate, W_k, PE_eff, N_ex, likelihood increment) to
+ * d_traj[i][f] (device, caller-owned, n_steps x F pf_master_t, 8-byte
+ * aligned), so a tracker gets the estimate of every frame without a host
+ * synchronization.  Iterations then run one launch each (never the
+ * multi-iteration launch).  d_traj may be NULL (then this is pf_run).
+ * Enqueue only. */
+int pf_run_traj(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
+                pf_master_t *d_traj);
 
 /* pf_run that also times every launch with a pair of HIP events recorded on
  * the context's stream around it, then synchronizes the stream.  host_ms_out

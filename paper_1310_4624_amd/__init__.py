@@ -8,4 +8,5 @@ from ._native import (PF_INIT_INFOSHARE, PF_INIT_TRACKING, PF_LIK_PATCH, PF_LIK_
                       PF_LIK_POISSON,
                       PF_MODE_ARNA, PF_MODE_RNA, PF_DEBUG_LINEAGE, PF_DEBUG_TRACE, PFError,
                       PF_LAUNCH_AUTO, PF_LAUNCH_PERSISTENT, PF_LAUNCH_STEPWISE)
-from .tracker import Batch, Tracker, nex, philox, resample_q, ring  # noqa: F401
+from .tracker import (TRAJ_RECORD_BYTES, Batch, Tracker, nex, philox, resample_q, ring,  # noqa: F401
+                      trajectory)

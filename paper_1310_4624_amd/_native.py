@@ -65,6 +65,18 @@ class pf_estimate_t(ctypes.Structure):
     ]
 
 
+class pf_master_t(ctypes.Structure):
+    _fields_ = [
+        ("xhat", ctypes.c_double * 5),
+        ("log_mass_glob", ctypes.c_double),
+        ("pe_eff", ctypes.c_double),
+        ("log_z_inc", ctypes.c_double),
+        ("n_ex", ctypes.c_uint32),
+        ("n_ex_next", ctypes.c_uint32),
+        ("step", ctypes.c_uint64),
+    ]
+
+
 class pf_pe_record(ctypes.Structure):
     _fields_ = [
         ("log_mass", ctypes.c_double),
@@ -82,6 +94,7 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_void_p)]),
     "pf_step": (ctypes.c_int, [_P, _P]),
     "pf_run": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64]),
+    "pf_run_traj": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64, _P]),
     "pf_run_timed": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint64,
                                     ctypes.POINTER(ctypes.c_float)]),
     "pf_run_info": (ctypes.c_int, [_P, _U32P]),

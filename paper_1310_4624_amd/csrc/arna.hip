@@ -82,7 +82,7 @@ struct pf_ctx {
     unsigned long long *bar;
     unsigned long long bar_timeout;
     StepArgs *run_args;            // [kRunMaxSteps] arguments of a k_run launch
-    EstDev *est;
+    pf_master_t *est;              // [F] master steps for pf_estimate
     DebugBufs *d_dbg;              // device copy of the debug-buffer table, or NULL
     // trace buffers
     uint32_t *t_pred, *t_q, *t_anc, *t_v;
@@ -443,7 +443,21 @@ bool run_allowed(const pf_ctx *c) {
 // iteration, or any iteration while run_allowed is false, is a k_step launch.
 // With ms_out, each launch is timed by a pair of events on the stream and
 // every iteration of it is given the launch's time divided by its length.
-int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out) {
+// The master step of the latest iteration (records of the current buffer)
+// to out[F].
+int launch_global(pf_ctx *c, pf_master_t *out) {
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
+    hipLaunchKernelGGL(k_global, dim3(c->cfg.n_filters), dim3(256), 0, c->stream, cur_rec(c), out,
+                       c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex, c->cutoff_ppm,
+                       (const uint32_t *)c->nex_used, (uint64_t)c->step);
+    HIP_OK(hipGetLastError());
+    return PF_OK;
+}
+
+// With traj, the master step of every iteration goes to traj[i][F] (one
+// launch per iteration then).
+int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out,
+              pf_master_t *traj = nullptr) {
     const bool timed = ms_out != nullptr;
     std::vector<hipEvent_t> ev;
     std::vector<uint32_t> len_of;   // iterations of each timed launch
@@ -470,7 +484,7 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
             }
         }
         uint32_t len = 1;
-        if (run_allowed(c)) {
+        if (run_allowed(c) && !traj) {
             rc = ensure_ring(c, k);
             if (rc != PF_OK) break;
             len = n - done < kRunMaxSteps ? n - done : kRunMaxSteps;
@@ -483,6 +497,8 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
         const float *frame = frames + (size_t)done * stride;
         if (len == 1) {
             rc = launch_step(c, frame);
+            if (rc == PF_OK && traj)
+                rc = launch_global(c, traj + (size_t)done * c->cfg.n_filters);
         } else {
             RunPrep pr;
             memset(&pr, 0, sizeof(pr));
@@ -727,6 +743,13 @@ int pf_run(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_st
     return run_steps(c, d_frames, n_steps, frame_stride, nullptr);
 }
 
+int pf_run_traj(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
+                pf_master_t *d_traj) {
+    if (!c || (!d_frames && n_steps)) return PF_EINVAL;
+    if ((uintptr_t)d_traj % alignof(pf_master_t)) return PF_EINVAL;
+    return run_steps(c, d_frames, n_steps, frame_stride, nullptr, d_traj);
+}
+
 int pf_run_timed(pf_ctx *c, const float *d_frames, uint32_t n_steps, uint64_t frame_stride,
                  float *host_ms_out) {
     if (!c || !host_ms_out || (!d_frames && n_steps)) return PF_EINVAL;
@@ -760,24 +783,18 @@ int pf_exchange(pf_ctx *c, int64_t *d_src_map) {
 
 int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
     if (!c || !o) return PF_EINVAL;
-    const uint32_t F = c->cfg.n_filters, M = c->cfg.n_pe;
-    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    hipLaunchKernelGGL(k_global, dim3(F), dim3(256), 0, c->stream, cur_rec(c), c->est, M,
-                       c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex, c->cutoff_ppm);
-    HIP_OK(hipGetLastError());
-    EstDev *e = (EstDev *)malloc(sizeof(EstDev) * F);
-    uint32_t *nex = (uint32_t *)malloc(sizeof(uint32_t) * F);
+    const uint32_t F = c->cfg.n_filters;
+    int rc = launch_global(c, c->est);
+    if (rc != PF_OK) return rc;
+    pf_master_t *e = (pf_master_t *)malloc(sizeof(pf_master_t) * F);
     pf_pe_record *rec = nullptr;
     const bool want_pe = o->x_pe || o->log_mass_pe;
     if (want_pe) rec = (pf_pe_record *)malloc(sizeof(pf_pe_record) * c->FM);
     uint32_t err = 0;
-    int rc = PF_OK;
-    if (!e || !nex || (want_pe && !rec)) rc = PF_ENOMEM;
+    if (!e || (want_pe && !rec)) rc = PF_ENOMEM;
     if (rc == PF_OK &&
-        (hipMemcpyAsync(e, c->est, sizeof(EstDev) * F, hipMemcpyDeviceToHost, c->stream) !=
+        (hipMemcpyAsync(e, c->est, sizeof(pf_master_t) * F, hipMemcpyDeviceToHost, c->stream) !=
              hipSuccess ||
-         hipMemcpyAsync(nex, c->nex_used, sizeof(uint32_t) * F, hipMemcpyDeviceToHost,
-                        c->stream) != hipSuccess ||
          hipMemcpyAsync(&err, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) !=
              hipSuccess ||
          (want_pe && hipMemcpyAsync(rec, cur_rec(c), sizeof(pf_pe_record) * c->FM,
@@ -790,9 +807,9 @@ int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
                 for (int d = 0; d < 5; ++d) o->x_global[5 * f + d] = e[f].xhat[d];
             if (o->log_mass_glob) o->log_mass_glob[f] = e[f].log_mass_glob;
             if (o->pe_eff) o->pe_eff[f] = e[f].pe_eff;
-            if (o->n_ex) o->n_ex[f] = nex[f];
+            if (o->n_ex) o->n_ex[f] = e[f].n_ex;
             if (o->n_ex_next) o->n_ex_next[f] = e[f].n_ex_next;
-            if (o->log_z_inc) o->log_z_inc[f] = e[f].log_z;
+            if (o->log_z_inc) o->log_z_inc[f] = e[f].log_z_inc;
         }
         if (want_pe)
             for (uint64_t i = 0; i < c->FM; ++i) {
@@ -807,7 +824,6 @@ int pf_estimate(pf_ctx *c, pf_estimate_t *o) {
             rc = PF_ENUMERIC;
     }
     free(e);
-    free(nex);
     free(rec);
     return rc;
 }

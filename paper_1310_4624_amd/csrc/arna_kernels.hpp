@@ -19,15 +19,6 @@ namespace {
 constexpr uint32_t kRingSteps = 64;     // iterations per ring-table batch
 constexpr int kRedDoubles = 128;        // LDS reduction scratch (>= 16 waves x 8)
 
-struct EstDev {                         // written by k_global, one per filter
-    double xhat[5];
-    double log_mass_glob;
-    double pe_eff;
-    double log_z;
-    uint32_t n_ex_next;
-    uint32_t pad;
-};
-
 // The master step of an iteration (Alg. 3 steps 9-10 and the input of step 2
 // of the next), per filter: log W = log sum_m W^(m) and the next N_ex.  For
 // many PEs it is computed once, by the last workgroup of the filter to
@@ -1041,10 +1032,12 @@ __global__ void k_identity(uint16_t *anc, uint32_t N, uint32_t np) {
 }
 
 // Master step of iteration k (Alg. 3, steps 9-10) for reporting: W_k, the
-// global estimate x_k = sum_m W^(m) x^m / W_k, PE_eff and the next N_ex.
-__global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, EstDev *est,
+// global estimate x_k = sum_m W^(m) x^m / W_k, PE_eff, the next N_ex and the
+// likelihood increment; n_ex is the N_ex iteration k used (nex_used[f]).
+__global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, pf_master_t *est,
                                                 uint32_t M, uint32_t np, uint32_t mode,
-                                                uint32_t fixed_nex, uint32_t cutoff_ppm) {
+                                                uint32_t fixed_nex, uint32_t cutoff_ppm,
+                                                const uint32_t *nex_used, uint64_t step) {
     __shared__ double red[kRedDoubles];
     const uint32_t f = blockIdx.x;
     const pf_pe_record *R = rec + (size_t)f * M;
@@ -1067,13 +1060,14 @@ __global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, EstDev 
     block_sum<6>(acc, red);
     block_sum_u64(sd, (uint64_t *)red);
     if (threadIdx.x == 0) {
-        EstDev o;
+        pf_master_t o;
         o.log_mass_glob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
         for (int c = 0; c < 5; ++c) o.xhat[c] = acc[1 + c] / acc[0];
         o.pe_eff = sd[1] ? (double)sd[0] * (double)sd[0] / (double)sd[1] : 0.0;
-        o.log_z = o.log_mass_glob - log((double)np);
+        o.log_z_inc = o.log_mass_glob - log((double)np);
+        o.n_ex = nex_used ? nex_used[f] : 0u;
         o.n_ex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
-        o.pad = 0;
+        o.step = step;
         est[f] = o;
     }
 }

@@ -21,6 +21,22 @@ DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=
                 block_size=0, launch=nat.PF_LAUNCH_AUTO)
 
 
+TRAJ_RECORD_BYTES = ctypes.sizeof(nat.pf_master_t)
+
+
+def trajectory(buf, n_steps: int, n_filters: int) -> dict:
+    """Decode the master steps pf_run_traj wrote ([n_steps][F] pf_master_t,
+    a CUDA uint8 tensor or host bytes) into arrays indexed [step][filter]."""
+    raw = buf[:n_steps * n_filters * TRAJ_RECORD_BYTES]
+    raw = raw.cpu().numpy() if hasattr(raw, "cpu") else np.asarray(raw, np.uint8)
+    dt = np.dtype([("xhat", "<f8", 5), ("log_mass_glob", "<f8"), ("pe_eff", "<f8"),
+                   ("log_z_inc", "<f8"), ("n_ex", "<u4"), ("n_ex_next", "<u4"),
+                   ("step", "<u8")])
+    assert dt.itemsize == TRAJ_RECORD_BYTES
+    rec = np.frombuffer(raw.tobytes(), dtype=dt).reshape(n_steps, n_filters)
+    return {k: rec[k].copy() for k in dt.names}
+
+
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
@@ -90,6 +106,25 @@ class Tracker:
         if stride != self.frame_numel():
             raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
         nat.check(nat.lib().pf_run(self._h, _dev_ptr(frames, "frames"), n, stride), "pf_run")
+
+    def run_traj(self, frames, traj, n_steps: int | None = None) -> None:
+        """Like run(); the master step of every iteration (Alg. 3 steps 9-10)
+        goes to ``traj``, a CUDA uint8 tensor of at least n_steps * F *
+        TRAJ_RECORD_BYTES bytes, without a host synchronization (read it back
+        with ``trajectory``)."""
+        import torch
+        n = frames.shape[0] if n_steps is None else n_steps
+        if n > frames.shape[0]:
+            raise ValueError("more steps than frames")
+        stride = int(np.prod(frames.shape[1:]))
+        if stride != self.frame_numel():
+            raise ValueError(f"frames hold {stride} values each, expected {self.frame_numel()}")
+        need = n * self.F * TRAJ_RECORD_BYTES
+        if (not isinstance(traj, torch.Tensor) or not traj.is_cuda or traj.dtype != torch.uint8
+                or not traj.is_contiguous() or traj.numel() < need):
+            raise TypeError(f"traj must be a contiguous CUDA uint8 tensor of >= {need} bytes")
+        nat.check(nat.lib().pf_run_traj(self._h, _dev_ptr(frames, "frames"), n, stride,
+                                        ctypes.c_void_p(traj.data_ptr())), "pf_run_traj")
 
     def run_timed(self, frames, n_steps: int | None = None) -> np.ndarray:
         """Like run(); returns each iteration's duration in ms (HIP events on

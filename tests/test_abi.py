@@ -49,6 +49,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", offsetof(pf_config, fixed_ratio), offsetof(pf_config, debug),
          offsetof(pf_config, seed), offsetof(pf_config, stream));
   printf("%zu %zu\\n", offsetof(pf_estimate_t, step), offsetof(pf_pe_record, lstar));
+  printf("%zu %zu %zu\\n", sizeof(pf_master_t), offsetof(pf_master_t, n_ex),
+         offsetof(pf_master_t, step));
   return 0;
 }
 """)
@@ -61,12 +63,13 @@ int main(void) {
             ctypes.sizeof(nat.pf_pe_record),
             nat.pf_config.fixed_ratio.offset, nat.pf_config.debug.offset,
             nat.pf_config.seed.offset, nat.pf_config.stream.offset,
-            nat.pf_estimate_t.step.offset, nat.pf_pe_record.lstar.offset]
+            nat.pf_estimate_t.step.offset, nat.pf_pe_record.lstar.offset,
+            ctypes.sizeof(nat.pf_master_t), nat.pf_master_t.n_ex.offset, nat.pf_master_t.step.offset]
     assert got == want
 
 
 def test_strerror_texts(L):
-    for code in [0, -1, -2, -3, -4, -5, -6]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
         assert L.pf_strerror(code)
     assert L.pf_strerror(-99) == b"unknown error"
 
