@@ -229,6 +229,23 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out);
  * run's argument table).  PF_ESTATE if a context is recording a gradient. */
 int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
                  uint32_t n_steps, int use_graph);
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): pf_batch_run without a graph, its
+ * argument table staged in a fixed device array of PF_BATCH_NOALLOC_MAX_ARGS
+ * entries (one per batched context and iteration, about 1 MiB) that the
+ * library holds on each GPU until the process ends, instead of a buffer the
+ * batch grows with hipMalloc.  The call allocates no device memory.
+ * n_steps x (contexts launched in groups) above PF_BATCH_NOALLOC_MAX_ARGS
+ * gives PF_EUNSUPPORTED before anything is enqueued.  The array is shared by
+ * every call on that GPU and keeps the last call's table: a call waits for
+ * the batch's stream before it overwrites the table, so calls on one stream
+ * are ordered, but calls that overlap on one GPU from different streams or
+ * threads race.  PF_EHIP if the array's address could not be taken when
+ * the contexts were created. */
+#define PF_BATCH_NOALLOC_MAX_ARGS 4096
+int pf_batch_run_noalloc(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                         uint32_t n_steps);
 void pf_batch_destroy(pf_batch *b);
 
 /* ------------------------------------------------------------- gradient */

@@ -21,6 +21,7 @@ PF_LAUNCH_AUTO, PF_LAUNCH_STEPWISE, PF_LAUNCH_PERSISTENT = 0, 1, 2
 PF_DEBUG_TRACE, PF_DEBUG_LINEAGE = 1, 2
 PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 4096, 15
 PF_MAX_PARTICLES = 1 << 29
+PF_BATCH_NOALLOC_MAX_ARGS = 4096
 
 DBG = dict(state=0, logmass=1, pe_records=2, ring=3, nex=4, src=5, prop=6, ell=7, q=8,
            ancestors=9, v=10, lam=11, lineage=12)
@@ -104,6 +105,7 @@ SIGNATURES = {
     "pf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pf_batch_create": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     "pf_batch_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, ctypes.c_int]),
+    "pf_batch_run_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32]),
     "pf_batch_destroy": (None, [_P]),
     "pf_grad_begin": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "pf_grad_end": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),

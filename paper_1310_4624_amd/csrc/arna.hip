@@ -22,6 +22,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -61,6 +62,7 @@ size_t step_lds(uint32_t np, bool lineage) { return lds_bytes(np, lineage); }
 struct pf_ctx {
     pf_config cfg;
     hipStream_t stream;
+    int device;                    // current device at pf_init
     uint64_t N, FM;
     uint32_t block, ppt, half;
     size_t lds;
@@ -133,7 +135,30 @@ struct pf_batch {
     std::vector<hipEvent_t> ev_join;
 };
 
+// Argument table of pf_batch_run_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code uses the address
+// hipGetSymbolAddress gave on each device (noalloc_args), never the name.
+static __device__ __align__(256) StepArgs scratch[PF_BATCH_NOALLOC_MAX_ARGS];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+StepArgs *noalloc_args[kMaxDevices];   // device address of `scratch` per device
+std::mutex noalloc_mu;
+
+// Takes the address of `scratch` on device dev (the current device), once.
+int noalloc_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return PF_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_args[dev]) return PF_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return PF_EHIP;
+    }
+    noalloc_args[dev] = (StepArgs *)p;
+    return PF_OK;
+}
 
 // From this many PEs per filter on, the master step is computed once per
 // filter (by its last workgroup) instead of by every PE of the next iteration.
@@ -585,6 +610,13 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     memset(c, 0, sizeof(*c));
     c->cfg = *cfg;
     c->stream = (hipStream_t)cfg->stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return PF_EHIP;
+    }
+    // the no-allocation batch entry point's table on this device (its failure
+    // only disables that entry point)
+    (void)noalloc_setup(c->device);
     const uint32_t F = cfg->n_filters, M = cfg->n_pe, np = cfg->n_per_pe;
     c->FM = (uint64_t)F * M;
     c->N = c->FM * np;
@@ -995,7 +1027,8 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
     *out = nullptr;
     if (!ctxs || n == 0) return PF_EINVAL;
     for (uint32_t i = 0; i < n; ++i) {
-        if (!ctxs[i] || ctxs[i]->stream != ctxs[0]->stream) return PF_EINVAL;
+        if (!ctxs[i] || ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
+            return PF_EINVAL;
         for (uint32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return PF_EINVAL;
     }
@@ -1070,8 +1103,14 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
     return PF_OK;
 }
 
-int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
-                 uint32_t n_steps, int use_graph) {
+}  // extern "C"
+
+namespace {
+
+// pf_batch_run; with `fixed` (cap entries) the argument table goes there
+// instead of the batch's own buffer, and nothing is allocated on the device.
+int batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+              uint32_t n_steps, int use_graph, StepArgs *fixed, size_t fixed_cap) {
     if (!b || !d_frames || !frame_stride) return PF_EINVAL;
     const uint32_t n = (uint32_t)b->ctx.size();
     for (uint32_t i = 0; i < n; ++i) {
@@ -1081,6 +1120,7 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
     }
     if (n_steps == 0) return PF_OK;
     const uint32_t nb = b->n_batched;
+    if (fixed && (uint64_t)n_steps * nb > fixed_cap) return PF_EUNSUPPORTED;
     // host pass: every batched context's arguments for every iteration, and
     // the ring tables each iteration has to rebuild first (rings[i]: context,
     // first iteration of the new table)
@@ -1125,7 +1165,7 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
         }
     };
     restore();
-    if (b->args_cap < args.size()) {
+    if (!fixed && b->args_cap < args.size()) {
         if (b->d_args) (void)hipFree(b->d_args);
         b->d_args = nullptr;
         b->args_cap = 0;
@@ -1133,9 +1173,9 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
         if (rc != PF_OK) return rc;
         b->args_cap = args.size();
     }
-    HIP_OK(hipStreamSynchronize(b->stream));   // earlier runs may still read d_args
-    HIP_OK(hipMemcpy(b->d_args, args.data(), args.size() * sizeof(StepArgs),
-                     hipMemcpyHostToDevice));
+    StepArgs *const d_args = fixed ? fixed : b->d_args;
+    HIP_OK(hipStreamSynchronize(b->stream));   // earlier runs may still read the table
+    HIP_OK(hipMemcpy(d_args, args.data(), args.size() * sizeof(StepArgs), hipMemcpyHostToDevice));
     // graph mode: the launches are captured from a private stream (the legacy
     // stream cannot be captured) and the graph is launched on the batch's
     const hipStream_t run_stream = b->stream;
@@ -1170,7 +1210,7 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
             if (rc != PF_OK) break;
             auto &g = b->groups[gi];
-            const StepArgs *ga = b->d_args + (size_t)t * nb + slot;
+            const StepArgs *ga = d_args + (size_t)t * nb + slot;
             uint32_t cnt = (uint32_t)g.members.size();
             void *kargs[] = {&ga, &g.d_first, &cnt};
             if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds,
@@ -1213,6 +1253,24 @@ int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *fram
         if (rc != PF_OK) (void)hipGetLastError();
     }
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                 uint32_t n_steps, int use_graph) {
+    return batch_run(b, d_frames, frame_stride, n_steps, use_graph, nullptr, 0);
+}
+
+int pf_batch_run_noalloc(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                         uint32_t n_steps) {
+    if (!b) return PF_EINVAL;
+    const int dev = b->ctx[0]->device;
+    StepArgs *table = (dev >= 0 && dev < kMaxDevices) ? noalloc_args[dev] : nullptr;
+    if (!table) return PF_EHIP;
+    return batch_run(b, d_frames, frame_stride, n_steps, 0, table, PF_BATCH_NOALLOC_MAX_ARGS);
 }
 
 void pf_batch_destroy(pf_batch *b) {

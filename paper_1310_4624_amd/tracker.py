@@ -323,8 +323,13 @@ class Batch:
                   "pf_batch_create")
         self._h = h
 
-    def run(self, frames, n_steps: int | None = None, graph: bool = False) -> None:
-        """frames[i]: the frames of tracker i (first axis = iteration)."""
+    def run(self, frames, n_steps: int | None = None, graph: bool = False,
+            no_alloc: bool = False) -> None:
+        """frames[i]: the frames of tracker i (first axis = iteration).
+        no_alloc: the entry point that allocates no device memory (argument
+        table in the library's fixed per-GPU array; no graph)."""
+        if no_alloc and graph:
+            raise ValueError("the no-allocation run has no graph mode")
         if len(frames) != len(self.trackers):
             raise ValueError("one frame stack per tracker")
         n = min(f.shape[0] for f in frames) if n_steps is None else n_steps
@@ -339,7 +344,10 @@ class Batch:
             strides.append(stride)
         P = (ctypes.c_void_p * len(ptrs))(*ptrs)
         S = (ctypes.c_uint64 * len(strides))(*strides)
-        nat.check(nat.lib().pf_batch_run(self._h, P, S, n, 1 if graph else 0), "pf_batch_run")
+        if no_alloc:
+            nat.check(nat.lib().pf_batch_run_noalloc(self._h, P, S, n), "pf_batch_run_noalloc")
+        else:
+            nat.check(nat.lib().pf_batch_run(self._h, P, S, n, 1 if graph else 0), "pf_batch_run")
 
     def close(self) -> None:
         h = getattr(self, "_h", None)

@@ -128,6 +128,7 @@ def test_null_arguments_rejected(L):
     out = ctypes.c_void_p()
     assert L.pf_batch_create(None, 0, ctypes.byref(out)) == nat.PF_EINVAL
     assert L.pf_batch_run(None, None, None, 1, 0) == nat.PF_EINVAL
+    assert L.pf_batch_run_noalloc(None, None, None, 1) == nat.PF_EINVAL
     L.pf_batch_destroy(None)
 
 
@@ -160,8 +161,9 @@ def test_build_flags_target_gfx950_without_packed_fp32():
 def test_limit_constants_match_header():
     """The binding's size limits are the header's #defines."""
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
-    defs = dict(re.findall(r"#define\s+(PF_MAX_\w+)\s+(.+)", text))
-    assert set(defs) == {"PF_MAX_PE", "PF_MAX_PER_PE", "PF_MAX_PATCH", "PF_MAX_PARTICLES"}
+    defs = dict(re.findall(r"#define\s+(PF_\w*MAX_\w+)\s+(.+)", text))
+    assert set(defs) == {"PF_MAX_PE", "PF_MAX_PER_PE", "PF_MAX_PATCH", "PF_MAX_PARTICLES",
+                         "PF_BATCH_NOALLOC_MAX_ARGS"}
     for name, expr in defs.items():
         val = eval(re.sub(r"(\d+)u\b", r"\1", expr.strip()), {})
         assert getattr(nat, name) == val, name

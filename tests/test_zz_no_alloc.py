@@ -1,0 +1,91 @@
+"""The batch entry point that allocates no device memory
+(pf_batch_run_noalloc): its argument table lives in the library's fixed
+per-GPU array, and every result is bitwise that of pf_batch_run on identical
+contexts, over two calls in a row (the second with fewer iterations, so the
+array still holds the first call's longer table), and a run too long for the
+array is refused before anything is enqueued."""
+import numpy as np
+import pytest
+
+from paper_1310_4624_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+BASE = dict(patch=9, init_mode=0, fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99,
+            psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5)
+CASES = [
+    dict(BASE, n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, mode=1, lik_mode=0, seed=61),
+    dict(BASE, n_filters=2, n_pe=8, n_per_pe=300, width=96, height=80, mode=1, lik_mode=0, seed=62),
+    dict(BASE, n_filters=1, n_pe=6, n_per_pe=2500, width=128, height=128, mode=1, lik_mode=0,
+         seed=63),
+    dict(BASE, n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, mode=0, lik_mode=1,
+         fixed_ratio=0.5, noise_sigma=1.0, seed=64),
+    dict(BASE, n_filters=1, n_pe=3, n_per_pe=200, width=64, height=64, mode=1, lik_mode=0,
+         patch=7, seed=65),                                      # launched alone inside the run
+]
+
+
+def _inputs(cfg, K, rng):
+    F = cfg["n_filters"]
+    if cfg["lik_mode"] == 1:
+        truth, obs = synth.point_sequence(int(rng.integers(1 << 30)), F, K)
+        return truth[0].astype(np.float32), obs
+    truth = np.zeros((F, 5), np.float32)
+    truth[:, 0] = rng.uniform(20, cfg["width"] - 20, F)
+    truth[:, 1] = rng.uniform(20, cfg["height"] - 20, F)
+    truth[:, 2:4] = rng.uniform(-0.5, 0.5, (F, 2))
+    truth[:, 4] = 12.0
+    frames = []
+    for k in range(K):
+        t = truth.astype(np.float64).copy()
+        t[:, :2] += (k + 1) * t[:, 2:4]
+        frames.append(synth.render(t, cfg["width"], cfg["height"], 1.5, 5.0, 2.0, rng))
+    return truth, np.stack(frames).astype(np.float32)
+
+
+def _outputs(t):
+    e = t.estimate()
+    return [t.debug_get("state"), t.debug_get("pe_records")] + [
+        np.asarray(e[k]) for k in ("x_global", "log_mass_glob", "pe_eff", "n_ex", "n_ex_next",
+                                   "step")]
+
+
+def test_no_alloc_batch_equals_batch_run():
+    import paper_1310_4624_amd as p
+    rng = np.random.Generator(np.random.PCG64(77))
+    K1, K2 = 30, 7
+    inputs = [_inputs(c, K1 + K2, rng) for c in CASES]
+    frames = [torch.from_numpy(np.ascontiguousarray(fr)).cuda() for _, fr in inputs]
+    ref = [p.Tracker(c, truth) for c, (truth, _) in zip(CASES, inputs)]
+    got = [p.Tracker(c, truth) for c, (truth, _) in zip(CASES, inputs)]
+    bref, bgot = p.Batch(ref), p.Batch(got)
+    for lo, hi in ((0, K1), (K1, K1 + K2)):
+        print(f"iterations {lo}..{hi}", flush=True)
+        bref.run([f[lo:hi] for f in frames])
+        bgot.run([f[lo:hi] for f in frames], no_alloc=True)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(ref, got)):
+            for x, y in zip(_outputs(a), _outputs(b)):
+                assert np.array_equal(x, y, equal_nan=True), (i, lo)
+    # more iterations than the array holds: refused, nothing advanced
+    n_rows = 4                      # contexts launched in groups (the patch-7 one is alone)
+    too_many = p._native.PF_BATCH_NOALLOC_MAX_ARGS // n_rows + 1
+    long = [torch.zeros((too_many, *f.shape[1:]), dtype=torch.float32, device="cuda")
+            for f in frames]
+    with pytest.raises(p.PFError) as err:
+        bgot.run(long, no_alloc=True)
+    assert err.value.code == p._native.PF_EUNSUPPORTED
+    assert all(t.estimate()["step"] == K1 + K2 for t in got)
+    bref.close()
+    bgot.close()
+    for t in ref + got:
+        t.close()
