@@ -19,6 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "arna_oracle.c")
+# ARNA_ORACLE_LIB names another build of the same source (the sanitizer test
+# loads an ASan/UBSan build this way); it is used as it is, never rebuilt.
+_LIB_OVERRIDE = os.environ.get("ARNA_ORACLE_LIB")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_RNA, MODE_ARNA = 0, 1
@@ -42,6 +45,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
+        if _LIB_OVERRIDE:
+            _lib = ctypes.CDLL(_LIB_OVERRIDE)
+            _declare(_lib)
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         _lib = ctypes.CDLL(_LIB)

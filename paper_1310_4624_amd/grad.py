@@ -52,7 +52,15 @@ _FN = None
 
 def log_marginal(theta, frames, cfg: dict, truth):
     """J [F] = log p-hat(z_1..z_K) per filter, differentiable in theta
-    (float64 tensor [3]: psf_sigma, I0, q).  frames: CUDA float32 [K][H][W]."""
+    (float64 tensor [3]: psf_sigma, I0, q).  frames: CUDA float32 [K][H][W].
+
+    Tracking start only: the information-sharing start draws the intensities
+    of PEs other than the first as 2 I0 u (a scaling of I0, not the shift
+    the reverse sweep differentiates), so it is refused."""
+    from ._native import PF_INIT_INFOSHARE
+    if cfg.get("init_mode", 0) == PF_INIT_INFOSHARE:
+        raise ValueError("log_marginal differentiates the tracking start only "
+                         "(init_mode=PF_INIT_TRACKING)")
     global _FN
     if _FN is None:
         _FN = _function()

@@ -1,0 +1,195 @@
+// Checks of the HIP library run on the CPU under the emulation in
+// emu_rt.cpp, built with AddressSanitizer and UndefinedBehaviorSanitizer:
+//   batch K MODE   nine contexts stepped alone and then together through
+//                  pf_batch_run (MODE 0), its graph mode (1) or
+//                  pf_batch_run_noalloc (2); results compared bit for bit
+#include "src/arna.hip"
+#include <random>
+#include <vector>
+
+// (the multi-iteration kernel is not built here: its cooperative launch
+// needs every workgroup resident at once)
+void *arna_run_kernel(uint32_t, uint32_t, uint32_t) { return nullptr; }
+extern "C" void emu_set_fill(int v);
+// CPU emulation of the batched-run test: nine contexts stepped alone and then
+// together (pf_batch_run), results compared bit for bit; ASan watches every
+// device buffer and the LDS block of every workgroup.
+
+struct Case {
+    uint32_t F, M, np, W, H, mode, lik, patch, block, groups;
+    float fixed, bg, noise;
+    uint64_t seed;
+};
+
+static pf_config make_cfg(const Case &c) {
+    pf_config p;
+    memset(&p, 0, sizeof(p));
+    p.struct_size = sizeof(pf_config);
+    p.n_filters = c.F; p.n_pe = c.M; p.n_per_pe = c.np; p.width = c.W; p.height = c.H;
+    p.patch = c.patch; p.mode = c.mode; p.init_mode = 0; p.lik_mode = c.lik;
+    p.fixed_ratio = c.fixed; p.initial_ratio = 0.1f; p.eff_cutoff = 0.99f; p.psf_sigma = 1.5f;
+    p.background = c.bg; p.noise_sigma = c.noise; p.q = 0.5f; p.sigma_I = 0.5f;
+    p.debug = 0; p.ring_groups = c.groups; p.block_size = c.block; p.launch = 0; p.seed = c.seed;
+    p.stream = nullptr;
+    return p;
+}
+
+struct Inputs { std::vector<float> truth, frames; uint64_t stride; };
+
+static Inputs make_inputs(const Case &c, int K, std::mt19937_64 &rng) {
+    Inputs in;
+    std::uniform_real_distribution<double> U(0, 1);
+    std::normal_distribution<double> Nd(0, 1);
+    in.truth.assign(5 * c.F, 0.f);
+    for (uint32_t f = 0; f < c.F; ++f) {
+        in.truth[5 * f + 0] = 20 + U(rng) * (c.W - 40);
+        in.truth[5 * f + 1] = 20 + U(rng) * (c.H - 40);
+        in.truth[5 * f + 2] = U(rng) - 0.5;
+        in.truth[5 * f + 3] = U(rng) - 0.5;
+        in.truth[5 * f + 4] = 12.f;
+    }
+    if (c.lik == PF_LIK_POINT) {
+        in.stride = 2 * c.F;
+        for (int k = 0; k < K; ++k)
+            for (uint32_t f = 0; f < c.F; ++f) {
+                in.frames.push_back(in.truth[5 * f] + (k + 1) * in.truth[5 * f + 2] + Nd(rng));
+                in.frames.push_back(in.truth[5 * f + 1] + (k + 1) * in.truth[5 * f + 3] + Nd(rng));
+            }
+        return in;
+    }
+    in.stride = (uint64_t)c.W * c.H;
+    for (int k = 0; k < K; ++k) {
+        for (uint32_t y = 0; y < c.H; ++y)
+            for (uint32_t x = 0; x < c.W; ++x) {
+                double mu = c.bg;
+                for (uint32_t f = 0; f < c.F; ++f) {
+                    const double px = in.truth[5 * f] + (k + 1) * in.truth[5 * f + 2];
+                    const double py = in.truth[5 * f + 1] + (k + 1) * in.truth[5 * f + 3];
+                    mu += 12.0 * exp(-((x - px) * (x - px) + (y - py) * (y - py)) / (2 * 1.5 * 1.5));
+                }
+                double z;
+                if (c.lik == PF_LIK_POISSON) {
+                    std::poisson_distribution<int> P(mu);
+                    z = P(rng);
+                } else {
+                    z = mu + c.noise * Nd(rng);
+                }
+                in.frames.push_back((float)z);
+            }
+    }
+    return in;
+}
+
+struct Result { std::vector<float> st; std::vector<unsigned char> rec; std::vector<double> xg, lg, pe; std::vector<uint32_t> nex, nexn; uint64_t step; };
+
+static void check(int rc, const char *w) {
+    if (rc != PF_OK) { fprintf(stderr, "%s: %s (%d)\n", w, pf_strerror(rc), rc); exit(1); }
+}
+
+static Result grab(pf_ctx *c, const Case &cs) {
+    Result r;
+    r.st.resize(pf_debug_size(c, PF_DBG_STATE) / 4);
+    check(pf_debug_get(c, PF_DBG_STATE, r.st.data(), r.st.size() * 4), "state");
+    r.rec.resize(pf_debug_size(c, PF_DBG_PE_RECORDS));
+    check(pf_debug_get(c, PF_DBG_PE_RECORDS, r.rec.data(), r.rec.size()), "rec");
+    r.xg.resize(5 * cs.F); r.lg.resize(cs.F); r.pe.resize(cs.F); r.nex.resize(cs.F); r.nexn.resize(cs.F);
+    pf_estimate_t e;
+    memset(&e, 0, sizeof(e));
+    e.x_global = r.xg.data(); e.log_mass_glob = r.lg.data(); e.pe_eff = r.pe.data();
+    e.n_ex = r.nex.data(); e.n_ex_next = r.nexn.data();
+    check(pf_estimate(c, &e), "estimate");
+    r.step = e.step;
+    return r;
+}
+
+static int batch_main(int K, int graph) {
+    const int split = K > 40 ? 40 : K / 2;
+    std::vector<Case> cases = {
+        {1, 4, 256, 128, 128, 0, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 1},
+        {1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 2},
+        {2, 8, 300, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 3},
+        {1, 6, 2500, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 4},
+        {1, 4, 1000, 64, 48, 1, 2, 9, 0, 0, 0.1f, 10.f, 2.f, 5},
+        {3, 5, 77, 128, 128, 0, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 6},
+        {1, 3, 200, 64, 64, 1, 0, 7, 0, 0, 0.1f, 5.f, 2.f, 7},
+        {1, 5, 1000, 96, 80, 1, 0, 9, 512, 0, 0.1f, 5.f, 2.f, 8},
+        {2, 8, 100, 96, 80, 1, 0, 9, 0, 4, 0.1f, 5.f, 2.f, 9},
+    };
+    if (getenv("EMU_CASES")) {   // comma-free digit list, e.g. "0134"
+        std::vector<Case> sel;
+        for (const char *p = getenv("EMU_CASES"); *p; ++p) sel.push_back(cases[*p - '0']);
+        cases = sel;
+    }
+    std::mt19937_64 rng(2024);
+    std::vector<Inputs> ins;
+    for (auto &c : cases) ins.push_back(make_inputs(c, K, rng));
+    // device copies of the frames (plain host memory under the emulation)
+    std::vector<float *> dfr;
+    for (auto &in : ins) {
+        float *d;
+        hipMalloc(&d, in.frames.size() * 4);
+        memcpy(d, in.frames.data(), in.frames.size() * 4);
+        dfr.push_back(d);
+    }
+    std::vector<Result> solo;
+    for (size_t i = 0; i < cases.size(); ++i) {
+        pf_config cfg = make_cfg(cases[i]);
+        pf_ctx *c;
+        check(pf_init(&cfg, ins[i].truth.data(), &c), "init");
+        check(pf_run(c, dfr[i], split, ins[i].stride), "run a");
+        check(pf_run(c, dfr[i] + split * ins[i].stride, K - split, ins[i].stride), "run b");
+        solo.push_back(grab(c, cases[i]));
+        pf_destroy(c);
+        fprintf(stderr, "solo case %zu done\n", i);
+    }
+    std::vector<pf_ctx *> ctx(cases.size());
+    for (size_t i = 0; i < cases.size(); ++i) {
+        pf_config cfg = make_cfg(cases[i]);
+        check(pf_init(&cfg, ins[i].truth.data(), &ctx[i]), "init b");
+    }
+    pf_batch *b;
+    check(pf_batch_create(ctx.data(), (uint32_t)ctx.size(), &b), "batch create");
+    std::vector<const float *> p0, p1;
+    std::vector<uint64_t> strides;
+    for (size_t i = 0; i < cases.size(); ++i) {
+        p0.push_back(dfr[i]);
+        p1.push_back(dfr[i] + split * ins[i].stride);
+        strides.push_back(ins[i].stride);
+    }
+    if (graph == 2) {   // the entry point that allocates nothing
+        const int big = pf_batch_run_noalloc(b, p0.data(), strides.data(), 100000);
+        fprintf(stderr, "oversized no-alloc run: %d\n", big);
+        if (big != PF_EUNSUPPORTED) return 3;
+        check(pf_batch_run_noalloc(b, p0.data(), strides.data(), split), "noalloc a");
+        check(pf_batch_run_noalloc(b, p1.data(), strides.data(), K - split), "noalloc b");
+    } else {
+        check(pf_batch_run(b, p0.data(), strides.data(), split, graph), "batch a");
+        check(pf_batch_run(b, p1.data(), strides.data(), K - split, graph), "batch b");
+    }
+    int bad = 0;
+    for (size_t i = 0; i < cases.size(); ++i) {
+        Result r = grab(ctx[i], cases[i]);
+        const Result &s = solo[i];
+        const bool eq = r.st == s.st && r.rec == s.rec && r.xg == s.xg && r.lg == s.lg &&
+                        r.pe == s.pe && r.nex == s.nex && r.nexn == s.nexn && r.step == s.step;
+        size_t nd = 0;
+        for (size_t j = 0; j < r.st.size(); ++j) nd += memcmp(&r.st[j], &s.st[j], 4) != 0;
+        fprintf(stderr, "case %zu: batch %s solo (state values differing: %zu of %zu), step %llu\n", i,
+                eq ? "==" : "!=", nd, r.st.size(), (unsigned long long)r.step);
+        bad += !eq;
+    }
+    pf_batch_destroy(b);
+    for (auto c : ctx) pf_destroy(c);
+    for (auto d : dfr) hipFree(d);
+    fprintf(stderr, bad ? "MISMATCH\n" : "ALL EQUAL\n");
+    return bad ? 2 : 0;
+}
+
+int main(int argc, char **argv) {
+    if (argc > 1 && !strcmp(argv[1], "batch")) {
+        if (argc > 4) emu_set_fill(atoi(argv[4]));
+        return batch_main(argc > 2 ? atoi(argv[2]) : 70, argc > 3 ? atoi(argv[3]) : 0);
+    }
+    fprintf(stderr, "usage: %s batch K MODE [FILL]\n", argv[0]);
+    return 1;
+}

@@ -66,9 +66,12 @@ def test_batch_equals_separate_runs(graph):
     K = 70   # crosses the ring table rebuild at iteration 65
     cases = _cases()
     inputs = [_inputs(c, K, rng) for c in cases]
+    print("inputs drawn", flush=True)
     frames = [torch.from_numpy(np.ascontiguousarray(fr)).cuda() for _, fr in inputs]
+    print("frames on the device", flush=True)
     solo = []
-    for c, (truth, _), fr in zip(cases, inputs, frames):
+    for i, (c, (truth, _), fr) in enumerate(zip(cases, inputs, frames)):
+        print(f"solo case {i}: {c['n_filters']}x{c['n_pe']}x{c['n_per_pe']}", flush=True)
         t = p.Tracker(c, truth)
         t.run(fr[:40])
         t.run(fr[40:K])
@@ -76,8 +79,11 @@ def test_batch_equals_separate_runs(graph):
         t.close()
     trs = [p.Tracker(c, truth) for c, (truth, _) in zip(cases, inputs)]
     b = p.Batch(trs)
+    print(f"batch run (graph={graph})", flush=True)
     b.run([f[:40] for f in frames], graph=graph)
     b.run([f[40:K] for f in frames], graph=graph)
+    torch.cuda.synchronize()
+    print("batch run done", flush=True)
     for t, (st, rec, est) in zip(trs, solo):
         assert np.array_equal(t.debug_get("state"), st)
         assert np.array_equal(t.debug_get("pe_records"), rec)
