@@ -2,16 +2,22 @@
 
 A step is one full iteration of the hot path (ring, exchange ratio, exchange,
 renormalization, propagation, patch likelihood, per-PE reductions, systematic
-resampling, PE records) over all particles of the workload, frames already
-resident in HBM.  Prints one JSON line.
+resampling, PE records, and the master step: global estimate, W_k, PE_eff,
+next N_ex and likelihood increment, written to a device trajectory buffer)
+over all particles of the workload, frames already resident in HBM.  Prints
+one JSON line.
 
 Default workload: the ARNA tracking configuration, 4 filters x 64 PEs x 4096
-particles (2^20 particles), 512 x 512 frames with 4 spots of SNR 2..6.
+particles (2^20 particles), 512 x 512 frames with 4 spots of SNR 2..6; the
+information-sharing configuration (1 x 256 x 4096) is measured the same way
+and reported beside it.
 
-Timing: after the warm-up, one pf_run of K steps is bracketed by two HIP
-events on the stream the kernels run on (the metric).  A second region of
-steps, each bracketed by events that the library records on the same stream,
-gives the step kernel's average duration for the roofline entry.
+Timing: after the warm-up, one pf_run_traj of K steps (K = 64 by default, so
+that an ARNA run rebuilds its ring table once inside the region) is bracketed
+by two HIP events on the stream the kernels run on (the metric).  A second
+region of steps, each bracketed by events that the library records on the same
+stream around its step launch, gives the step kernel's average duration for
+the roofline entry.
 """
 from __future__ import annotations
 
@@ -38,6 +44,8 @@ STATE_BYTES = 40.0
 KERNEL_SOURCES = ["paper_1310_4624_amd/csrc/arna_kernels.hpp",
                   "paper_1310_4624_amd/csrc/arna_device.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+HEADLINE = "arna_tracking_512_4x64x4096"
+SECOND = "arna_infoshare_512_256x4096"
 
 
 def algorithmic_bytes(n_particles: int, width: int, height: int) -> float:
@@ -72,44 +80,81 @@ def measured_counters(workload: str, ring_groups: int = 0):
 VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 
 
+def valu_entry(counters, kernel_ms: float, n_particles: int):
+    """VALU use of k_step from the counters in profiles/k_step_traffic.json:
+    instructions per particle-step, and the busy fraction from the counted
+    VALU cycles (SQ_ACTIVE_INST_VALU counts the cycles VALU instructions
+    occupy, so quarter-rate and transcendental instructions weigh what they
+    cost) over the SIMD cycles of the kernel's duration."""
+    if not counters or "valu_insts" not in counters:
+        return None
+    v = {"insts_per_launch": counters["valu_insts"],
+         "insts_per_particle_step": counters["valu_insts"] * 64.0 / n_particles,
+         "issue_ms_at_4_cycles": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3}
+    if "valu_active_cycles" in counters:
+        # SQ_ACTIVE_INST_VALU is summed over the waves; in units of 4 cycles
+        # per SIMD (quad-cycle counter), over 1024 SIMDs at 2.4 GHz
+        busy_s = counters["valu_active_cycles"] * 4.0 / 1024 / 2.4e9
+        v["busy_frac"] = busy_s * 1e3 / kernel_ms
+    for k in ("valu_busy_pct", "valu_by_class", "wait_inst_any"):
+        if k in counters:
+            v[k] = counters[k]
+    return v
+
+
 def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int, ring_groups: int = 0):
     import torch
     from paper_1310_4624_amd import Tracker, synth
 
+    from paper_1310_4624_amd import TRAJ_RECORD_BYTES, trajectory
+
     cfg = synth.filter_config(workload, seed=seed, ring_groups=ring_groups)
-    n_frames = max(warmup + steps + probe, synth.WORKLOADS[workload]["seq"]["frames"])
+    n_frames = max(warmup + 2 * steps + probe, synth.WORKLOADS[workload]["seq"]["frames"])
     seq = synth.make_sequence(workload, seed=1000, frames=n_frames)
     F = cfg["n_filters"]
     torch.cuda.set_device(0)
-    frames = torch.from_numpy(seq.frames[:warmup + steps + probe]).cuda()
+    frames = torch.from_numpy(seq.frames[:warmup + 2 * steps + probe]).cuda()
+    traj = torch.empty(max(steps, 1) * F * TRAJ_RECORD_BYTES, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     tr = Tracker(cfg, seq.initial_truth()[:F])
     if warmup:
         tr.run(frames[:warmup])
     torch.cuda.synchronize()
 
-    # timed region: K steps in one call, two events
+    # timed region: K steps in one call, every iteration's master step
+    # written to the device trajectory, two events
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    tr.run(frames[warmup:warmup + steps])
+    tr.run_traj(frames[warmup:warmup + steps], traj)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = e0.elapsed_time(e1)
+    tj = trajectory(traj, steps, F)
+
+    # context: the same number of steps without the per-iteration master
+    # record (pf_run)
+    e0.record(stream)
+    tr.run(frames[warmup + steps:warmup + 2 * steps])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
 
     # kernel-duration region: the library records a pair of HIP events around
-    # each launch on the same stream (no host round trip in between)
-    per = tr.run_timed(frames[warmup + steps:warmup + steps + probe]).astype(np.float64)
-    ks = warmup + steps + 1 + np.arange(probe)
+    # each step launch on the same stream (no host round trip in between)
+    lo = warmup + 2 * steps
+    per = tr.run_timed(frames[lo:lo + probe]).astype(np.float64)
+    ks = lo + 1 + np.arange(probe)
     # iterations k = 1, 65, 129, ... also build the next 64 rings (ARNA)
     ring = (ks - 1) % 64 == 0 if cfg["mode"] == 1 else np.zeros(probe, bool)
     step_ms = float(per[~ring].mean()) if (~ring).any() else float(per.mean())
-    est = tr.estimate()
     tr.close()
-    return dict(cfg=cfg, seq=seq, total_ms=total_ms, wall_s=wall, step_kernel_ms=step_ms,
-                pe_eff=est["pe_eff"].tolist(), n_ex=est["n_ex"].tolist())
+    return dict(cfg=cfg, seq=seq, total_ms=total_ms, plain_ms=plain_ms, wall_s=wall,
+                step_kernel_ms=step_ms, pe_eff=tj["pe_eff"][-1].tolist(),
+                n_ex=tj["n_ex"][-1].tolist(), log_z_sum=tj["log_z_inc"].sum(0).tolist(),
+                traj_steps=[int(tj["step"][0][0]), int(tj["step"][-1][0])] if steps else [])
 
 
 def grad_leg(workload: str, frames_n: int, seed: int):
@@ -166,14 +211,28 @@ def grad_leg(workload: str, frames_n: int, seed: int):
             "theta": ["psf_sigma", "I0", "q"]}
 
 
-def cpu_leg(workload: str, seed: int, budget_s: float, seq):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(workload: str, seed: int, budget_s: float, seq, threads: int = 0):
     """The FP64 oracle on the host cores: whole iterations of the same
-    workload on the same frames until the time budget is used (at least one).
-    When the frames run out before the budget, a new filter runs the sequence
-    again from its start (at most four passes)."""
+    workload on the same frames until the time budget is used (at least one),
+    with `threads` OpenMP threads (0: the runtime's default).  When the frames
+    run out before the budget, a new filter runs the sequence again from its
+    start (at most four passes)."""
     from oracle import oracle as orc
     from paper_1310_4624_amd import synth
 
+    default = orc.num_threads()
+    orc.set_num_threads(threads or default)
     cfg = synth.filter_config(workload, seed=seed)
     F = cfg["n_filters"]
     K = seq.frames.shape[0]
@@ -190,7 +249,9 @@ def cpu_leg(workload: str, seed: int, budget_s: float, seq):
         t += time.perf_counter() - t0
         i += 1
         done += 1
-    return dict(value=N * done / t, unit="particle-steps/s", cores=orc.num_threads(),
+    used = orc.num_threads()
+    orc.set_num_threads(default)
+    return dict(value=N * done / t, unit="particle-steps/s", cores=used,
                 kind="oracle",
                 sample=f"{workload}: {done} iterations ({passes} pass(es) over the first "
                        f"{min(done, K)} frames of the same sequence), {N} particles, "
@@ -202,15 +263,17 @@ def main():
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--probe", type=int, default=20, help="single steps timed for the roofline")
-    ap.add_argument("--workload", default="arna_tracking_512_4x64x4096",
-                    choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--second-workload", default=SECOND,
+                    help="measured the same way and reported under `workloads` ('' to skip)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--ring-groups", type=int, default=0,
                     help="ARNA hardware-aware ring with this many PE groups (8: one per die)")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work at all threads (a third of it at one thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad-workload", default="arna_grad_512_256x4096",
                     choices=sorted(synth.WORKLOADS))
@@ -236,15 +299,25 @@ def main():
               "multi-GPU sharding of the path is a design note, not code", file=sys.stderr)
         sys.exit(2)
 
+    def summary(g):
+        c = g["cfg"]
+        n = c["n_filters"] * c["n_pe"] * c["n_per_pe"]
+        ms_step = g["total_ms"] / max(args.steps, 1)
+        b_launch = algorithmic_bytes(n, c["width"], c["height"])
+        k_ms = g["step_kernel_ms"]
+        return dict(n=n, ms=ms_step, value=n * args.steps / (g["total_ms"] / 1e3),
+                    plain_ms=g["plain_ms"] / max(args.steps, 1), bytes_launch=b_launch,
+                    kernel_ms=k_ms, achieved=b_launch / (k_ms / 1e3) / 1e9)
+
     g = gpu_leg(args.workload, args.steps, args.warmup, args.seed, args.probe, args.ring_groups)
     cfg = g["cfg"]
-    N = cfg["n_filters"] * cfg["n_pe"] * cfg["n_per_pe"]
-    ms = g["total_ms"] / args.steps
-    value = N * args.steps / (g["total_ms"] / 1e3)
-    bytes_launch = algorithmic_bytes(N, cfg["width"], cfg["height"])
-    # average launch duration over the timed region (one launch per step; the
-    # region's events bracket the whole pf_run, so gaps between launches count)
-    achieved = bytes_launch / (ms / 1e3) / 1e9
+    h = summary(g)
+    N, ms, value = h["n"], h["ms"], h["value"]
+    # the roofline of the step kernel: algorithmic bytes of one launch over its
+    # average duration, from the events the library records around each step
+    # launch on the kernels' stream (the timed region's per-step time also
+    # holds the master-step launch and the gaps between launches)
+    achieved = h["achieved"]
     counters = measured_counters(args.workload, args.ring_groups)
     line = {
         "metric": METRIC,
@@ -264,21 +337,29 @@ def main():
                    "frame": f"{cfg['width']}x{cfg['height']}", "patch": cfg["patch"],
                    "mode": "ARNA" if cfg["mode"] == 1 else "RNA",
                    "ring_groups": cfg.get("ring_groups", 0),
+                   "master_step": "every iteration, to a device trajectory (pf_run_traj)",
                    "parallelism": "one PE per workgroup, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (counters or {}).get("bytes_per_launch"),
-                     "kernel": "k_step", "kernel_ms": ms,
-                     "event_ms_per_launch": g["step_kernel_ms"],
-                     "bytes_per_launch": bytes_launch, "kernel_sha": kernel_sha()},
-        "valu": None if not counters or "valu_insts" not in counters else {
-            "insts_per_launch": counters["valu_insts"],
-            "issue_ms": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3,
-            "busy_frac": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3 / ms,
-            "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S},
+                     "kernel": "k_step", "kernel_ms": h["kernel_ms"],
+                     "bytes_per_launch": h["bytes_launch"], "kernel_sha": kernel_sha(),
+                     "timed_region_ms_per_step": ms},
+        "ms_per_step_without_master_record": h["plain_ms"],
+        "valu": valu_entry(counters, h["kernel_ms"], N),
         "final_pe_eff": g["pe_eff"],
         "final_n_ex": g["n_ex"],
+        "log_z_sum": g["log_z_sum"],
     }
+    if args.second_workload:
+        g2 = gpu_leg(args.second_workload, args.steps, args.warmup, args.seed, args.probe,
+                     args.ring_groups)
+        h2 = summary(g2)
+        line["workloads"] = {
+            w: {"value": x["value"], "ms_per_step": x["ms"],
+                "ms_per_step_without_master_record": x["plain_ms"], "n_particles": x["n"],
+                "kernel_ms": x["kernel_ms"], "roofline_frac": x["achieved"] / HBM_PEAK_GBS}
+            for w, x in ((args.workload, h), (args.second_workload, h2))}
     if args.grad_frames:
         gl = grad_leg(args.grad_workload, args.grad_frames, args.seed)
         line["fwd_bwd_over_fwd"] = gl["fwd_bwd_over_fwd"]
@@ -287,7 +368,11 @@ def main():
         from paper_1310_4624_amd.experiments import batch
         line["batch"] = batch(frames=args.batch_frames)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_leg(args.workload, args.seed, args.cpu_budget, g["seq"])
+        cb = cpu_leg(args.workload, args.seed, args.cpu_budget, g["seq"])
+        one = cpu_leg(args.workload, args.seed, args.cpu_budget / 3, g["seq"], threads=1)
+        cb["cpu_model"] = cpu_model()
+        cb["single_thread"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

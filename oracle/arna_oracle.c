@@ -834,6 +834,16 @@ int orc_step(orc_filter *o, const float *frame, orc_trace *tr)
     return status;
 }
 
+/* Sets the OpenMP thread count of later calls (no effect without OpenMP). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Threads the OpenMP runtime will use (1 without OpenMP). */
 int orc_num_threads(void)
 {

@@ -123,6 +123,8 @@ def _declare(L):
                            ctypes.POINTER(_Trace)]
     L.orc_step.restype = i32
     L.orc_num_threads.restype = i32
+    L.orc_set_num_threads.restype = None
+    L.orc_set_num_threads.argtypes = [i32]
     PD = ctypes.POINTER(ctypes.c_double)
     L.orc_normals.argtypes = [u64, u32, u32, u32, PD]
     L.orc_propagate.argtypes = [PD, PD, ctypes.c_double, ctypes.c_double, PD]
@@ -242,6 +244,11 @@ def loglik(cfg, frame, f: int, state5) -> float:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------------ filter

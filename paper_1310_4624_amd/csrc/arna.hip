@@ -358,7 +358,8 @@ int ensure_ring(pf_ctx *c, uint64_t k, bool downward = false) {
     return launch_ring(c, base);
 }
 
-StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
+// traj_prev: the trajectory row of iteration k-1 that the step writes, or NULL.
+StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame, pf_master_t *traj_prev = nullptr) {
     StepArgs a;
     memset(&a, 0, sizeof(a));
     const int nxt = 1 - c->cur;
@@ -404,6 +405,7 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame) {
     a.lin_in = (uint32_t)c->cur;
     a.err = c->err;
     a.nex_used = c->nex_used;
+    a.traj_prev = c->mrec[0] ? nullptr : traj_prev;   // (many PEs: k_global writes the rows)
     return a;
 }
 
@@ -429,13 +431,13 @@ void advance(pf_ctx *c, uint64_t k) {
     c->exchanged = false;
 }
 
-int launch_step(pf_ctx *c, const float *frame) {
+int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr) {
     const uint64_t k = c->step + 1;
     if (k > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
     if (c->g_cap && c->g_len >= c->g_cap) return PF_ESTATE;   // tape full
     int rc = ensure_ring(c, k);
     if (rc != PF_OK) return rc;
-    StepArgs a = make_args(c, k, frame);
+    StepArgs a = make_args(c, k, frame, traj_prev);
     void *fn = pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
     if (!fn) return PF_EUNSUPPORTED;
     void *args[] = {&a};
@@ -472,15 +474,25 @@ bool run_allowed(const pf_ctx *c) {
 // to out[F].
 int launch_global(pf_ctx *c, pf_master_t *out) {
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    hipLaunchKernelGGL(k_global, dim3(c->cfg.n_filters), dim3(256), 0, c->stream, cur_rec(c), out,
-                       c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex, c->cutoff_ppm,
-                       (const uint32_t *)c->nex_used, (uint64_t)c->step);
+    // fewer PEs: one wave per filter, in the order of the step's prologue
+    if (c->cfg.n_pe < kMasterMinPE)
+        hipLaunchKernelGGL(k_global_wave, dim3(c->cfg.n_filters), dim3(kWave), 0, c->stream,
+                           cur_rec(c), out, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
+                           c->fixed_nex, c->cutoff_ppm, (const uint32_t *)c->nex_used,
+                           (uint64_t)c->step);
+    else
+        hipLaunchKernelGGL(k_global, dim3(c->cfg.n_filters), dim3(256), 0, c->stream, cur_rec(c),
+                           out, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex,
+                           c->cutoff_ppm, (const uint32_t *)c->nex_used, (uint64_t)c->step);
     HIP_OK(hipGetLastError());
     return PF_OK;
 }
 
-// With traj, the master step of every iteration goes to traj[i][F] (one
-// launch per iteration then).
+// With traj, the master step of every iteration goes to traj[i][F]: for
+// fewer than kMasterMinPE PEs the step of iteration i + 1 writes row i from
+// its prologue and one k_global_wave launch after the run writes the last
+// row; for more, a k_global launch follows every step.  Either way the
+// iterations run one launch each.
 int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out,
               pf_master_t *traj = nullptr) {
     const bool timed = ms_out != nullptr;
@@ -521,9 +533,10 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
         }
         const float *frame = frames + (size_t)done * stride;
         if (len == 1) {
-            rc = launch_step(c, frame);
-            if (rc == PF_OK && traj)
-                rc = launch_global(c, traj + (size_t)done * c->cfg.n_filters);
+            const size_t F = c->cfg.n_filters;
+            const bool fused = traj && !c->mrec[0];
+            rc = launch_step(c, frame, (fused && done) ? traj + (size_t)(done - 1) * F : nullptr);
+            if (rc == PF_OK && traj && !fused) rc = launch_global(c, traj + (size_t)done * F);
         } else {
             RunPrep pr;
             memset(&pr, 0, sizeof(pr));
@@ -565,6 +578,8 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
         }
         if (rc == PF_OK) done += len;
     }
+    if (rc == PF_OK && traj && n && !c->mrec[0])   // the last row
+        rc = launch_global(c, traj + (size_t)(n - 1) * c->cfg.n_filters);
     if (timed) {
         if (rc == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = PF_EHIP;
         uint32_t it = 0;

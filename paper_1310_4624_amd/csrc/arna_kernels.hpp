@@ -69,6 +69,10 @@ struct StepArgs {
     const MasterRec *min;
     MasterRec *mout;
     uint32_t *arrive;                   // [F] workgroups of the filter done with k
+    // [F] row of iteration k-1 of a caller's trajectory: wave 0 of PE (f, 0)
+    // writes the master step of k-1 there (the prologue reduces the same
+    // records); NULL: no row (first iteration of a run, or many PEs)
+    pf_master_t *traj_prev;
 };
 
 // What a PE knows after steps 1-2 (and the inputs of steps 3-4).
@@ -81,7 +85,10 @@ struct Prologue {
 // of every workgroup from the M records of the previous iteration:
 //   L_glob = log sum_m W^(m)_{k-1},  P_m = floor(exp(L_m - max L) 2^20),
 //   S = sum P, D = sum P^2  ->  N_ex (Eq. 3 with PE_eff = S^2 / D).
-// Lane 0 writes the result to `out`.
+// Lane 0 writes the result to `out`.  With a.traj_prev, PE 0 of the filter
+// also sums x_{k-1} = sum_m W^(m) x^m / W_{k-1} in the same loops and lane 0
+// writes the whole master step of k-1 (Alg. 3 steps 9-10) to the row; the
+// sums run in the order of k_global_wave, which gives the same bits.
 __device__ Prologue prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Prologue *out,
                                   const uint32_t tid) {
     // Latency first: the ring predecessor is loaded with the records, this
@@ -94,6 +101,8 @@ __device__ Prologue prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Pro
     const pf_pe_record *R = a.rin + (size_t)f * M;
     const uint32_t pred =
         (M == 1) ? m : (a.ring ? (uint32_t)a.ring[(size_t)f * M + m] : (m + M - 1) % M);
+    const bool want_x = m == 0 && a.traj_prev != nullptr;   // the same in every lane
+    double xs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double lv[kCached];
     double lmax = -INFINITY, l_own = 0.0, l_pred = 0.0;
 #pragma unroll
@@ -126,6 +135,9 @@ __device__ Prologue prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Pro
                 const uint64_t P = (uint64_t)floor(e * 1048576.0);
                 S += P;
                 D += P * P;
+                if (want_x && e > 0.0)   // (e = 0 past M)
+#pragma unroll
+                    for (int d = 0; d < 5; ++d) xs[d] += e * R[(uint32_t)c * kWave + lane].xhat[d];
             }
         }
         for (uint32_t i = kCached * kWave + lane; i < M; i += kWave) {
@@ -134,11 +146,30 @@ __device__ Prologue prologue_wave(const StepArgs &a, uint32_t f, uint32_t m, Pro
             const uint64_t P = (uint64_t)floor(e * 1048576.0);
             S += P;
             D += P * P;
+            if (want_x && e > 0.0)
+#pragma unroll
+                for (int d = 0; d < 5; ++d) xs[d] += e * R[i].xhat[d];
         }
     }
     acc = wave_sum(acc);
     S = wave_sum_u64(S);
     D = wave_sum_u64(D);
+    if (want_x) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d) xs[d] = wave_sum(xs[d]);
+        if (lane == 0) {
+            pf_master_t r;
+            r.log_mass_glob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) r.xhat[d] = xs[d] / acc;
+            r.pe_eff = D ? (double)S * (double)S / (double)D : 0.0;
+            r.log_z_inc = r.log_mass_glob - log((double)a.np);
+            r.n_ex = a.nex_used[f];   // (written at the end of k-1 by this PE)
+            r.n_ex_next = exchange_count(S, D, M, a.np, a.mode, 0, a.fixed_nex, 0, a.cutoff_ppm);
+            r.step = a.k - 1;
+            a.traj_prev[f] = r;
+        }
+    }
     // Every lane finishes the prologue (the wave executes it once either
     // way) and returns it: its integer fields (pred, N_ex, offsets) are the
     // same in every lane -- S and D are exact sums -- while the FP64 sum acc,
@@ -1069,6 +1100,79 @@ __global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, pf_mast
         o.n_ex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
         o.step = step;
         est[f] = o;
+    }
+}
+
+// k_global for M < kMasterMinPE with one wave per filter: the master step in
+// the order of prologue_wave's sums (records in chunks of 64 lanes, the first
+// kCached chunks, then the rest; wave butterflies), so that a trajectory row
+// written by the prologue and this kernel's record agree bit for bit.
+__global__ __launch_bounds__(64) void k_global_wave(const pf_pe_record *rec, pf_master_t *est,
+                                                    uint32_t M, uint32_t np, uint32_t mode,
+                                                    uint32_t fixed_nex, uint32_t cutoff_ppm,
+                                                    const uint32_t *nex_used, uint64_t step) {
+    constexpr int kCached = 4;
+    const uint32_t f = blockIdx.x, lane = threadIdx.x;
+    const pf_pe_record *R = rec + (size_t)f * M;
+    double lv[kCached];
+    double lmax = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < kCached; ++c) {
+        const uint32_t j0 = (uint32_t)c * kWave;
+        lv[c] = -INFINITY;
+        if (j0 < M) {
+            if (j0 + lane < M) lv[c] = R[j0 + lane].log_mass;
+            lmax = fmax(lmax, lv[c]);
+        }
+    }
+    for (uint32_t j0 = kCached * kWave; j0 < M; j0 += kWave) {
+        const double l = (j0 + lane < M) ? R[j0 + lane].log_mass : -INFINITY;
+        lmax = fmax(lmax, l);
+    }
+    lmax = wave_max_d(lmax);
+    double acc = 0.0, xs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    uint64_t S = 0, D = 0;
+    if (lmax != -INFINITY) {
+#pragma unroll
+        for (int c = 0; c < kCached; ++c) {
+            if ((uint32_t)c * kWave < M) {
+                const double e = exp(lv[c] - lmax);
+                acc += e;
+                const uint64_t P = (uint64_t)floor(e * 1048576.0);
+                S += P;
+                D += P * P;
+                if (e > 0.0)
+#pragma unroll
+                    for (int d = 0; d < 5; ++d) xs[d] += e * R[(uint32_t)c * kWave + lane].xhat[d];
+            }
+        }
+        for (uint32_t i = kCached * kWave + lane; i < M; i += kWave) {
+            const double e = exp(R[i].log_mass - lmax);
+            acc += e;
+            const uint64_t P = (uint64_t)floor(e * 1048576.0);
+            S += P;
+            D += P * P;
+            if (e > 0.0)
+#pragma unroll
+                for (int d = 0; d < 5; ++d) xs[d] += e * R[i].xhat[d];
+        }
+    }
+    acc = wave_sum(acc);
+    S = wave_sum_u64(S);
+    D = wave_sum_u64(D);
+#pragma unroll
+    for (int d = 0; d < 5; ++d) xs[d] = wave_sum(xs[d]);
+    if (lane == 0) {
+        pf_master_t r;
+        r.log_mass_glob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) r.xhat[d] = xs[d] / acc;
+        r.pe_eff = D ? (double)S * (double)S / (double)D : 0.0;
+        r.log_z_inc = r.log_mass_glob - log((double)np);
+        r.n_ex = nex_used ? nex_used[f] : 0u;
+        r.n_ex_next = exchange_count(S, D, M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
+        r.step = step;
+        est[f] = r;
     }
 }
 

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(1024) void k_run(RunArgs r) {
         a.min = nullptr;
         a.mout = nullptr;
         a.arrive = nullptr;
+        a.traj_prev = nullptr;
         a.lin_in = 0u;
         step_body<PPT, HALF, LIK, true>(a, b, xr, i > 0, t);
         if (i + 1 >= kp->n ||

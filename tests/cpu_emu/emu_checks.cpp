@@ -3,6 +3,7 @@
 //   batch K MODE   nine contexts stepped alone and then together through
 //                  pf_batch_run (MODE 0), its graph mode (1) or
 //                  pf_batch_run_noalloc (2); results compared bit for bit
+//   traj           pf_run_traj's rows against pf_estimate after each step
 #include "src/arna.hip"
 #include <random>
 #include <vector>
@@ -185,11 +186,66 @@ static int batch_main(int K, int graph) {
     return bad ? 2 : 0;
 }
 
+// pf_run_traj in two calls against a stepwise run with pf_estimate after
+// every iteration: the rows must be those estimates, bit for bit.
+static int traj_main() {
+    int bad = 0;
+    const Case cases[] = {
+        {2, 8, 300, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 3},
+        {1, 4, 256, 128, 128, 0, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 1},
+        {1, 300, 64, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},    // more than 256 PEs
+        {3, 5, 77, 128, 128, 1, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 6},
+    };
+    std::mt19937_64 rng(7);
+    for (const Case &cs : cases) {
+        const int K = 9;
+        Inputs in = make_inputs(cs, K, rng);
+        float *d;
+        hipMalloc(&d, in.frames.size() * 4);
+        memcpy(d, in.frames.data(), in.frames.size() * 4);
+        pf_config cfg = make_cfg(cs);
+        pf_ctx *a, *b;
+        check(pf_init(&cfg, in.truth.data(), &a), "init a");
+        check(pf_init(&cfg, in.truth.data(), &b), "init b");
+        pf_master_t *traj;
+        hipMalloc(&traj, sizeof(pf_master_t) * K * cs.F);
+        check(pf_run_traj(a, d, 4, in.stride, traj), "traj a");
+        check(pf_run_traj(a, d + 4 * in.stride, K - 4, in.stride, traj + 4 * cs.F), "traj b");
+        for (int k = 0; k < K; ++k) {
+            check(pf_step(b, d + k * in.stride), "step");
+            std::vector<double> xg(5 * cs.F), lg(cs.F), pe(cs.F), lz(cs.F);
+            std::vector<uint32_t> nx(cs.F), nn(cs.F);
+            pf_estimate_t e;
+            memset(&e, 0, sizeof(e));
+            e.x_global = xg.data(); e.log_mass_glob = lg.data(); e.pe_eff = pe.data();
+            e.n_ex = nx.data(); e.n_ex_next = nn.data(); e.log_z_inc = lz.data();
+            check(pf_estimate(b, &e), "estimate");
+            for (uint32_t f = 0; f < cs.F; ++f) {
+                const pf_master_t &r = traj[k * cs.F + f];
+                bool ok = r.step == (uint64_t)(k + 1) && !memcmp(r.xhat, &xg[5 * f], 40) &&
+                          !memcmp(&r.log_mass_glob, &lg[f], 8) && !memcmp(&r.pe_eff, &pe[f], 8) &&
+                          !memcmp(&r.log_z_inc, &lz[f], 8) && r.n_ex == nx[f] && r.n_ex_next == nn[f];
+                if (!ok) {
+                    fprintf(stderr, "M=%u row %d filter %u differs\n", cs.M, k, f);
+                    ++bad;
+                }
+            }
+        }
+        pf_destroy(a);
+        pf_destroy(b);
+        hipFree(traj);
+        hipFree(d);
+    }
+    fprintf(stderr, bad ? "TRAJ MISMATCH\n" : "TRAJ EQUAL\n");
+    return bad ? 2 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc > 1 && !strcmp(argv[1], "batch")) {
         if (argc > 4) emu_set_fill(atoi(argv[4]));
         return batch_main(argc > 2 ? atoi(argv[2]) : 70, argc > 3 ? atoi(argv[3]) : 0);
     }
-    fprintf(stderr, "usage: %s batch K MODE [FILL]\n", argv[0]);
+    if (argc > 1 && !strcmp(argv[1], "traj")) return traj_main();
+    fprintf(stderr, "usage: %s batch K MODE [FILL] | traj\n", argv[0]);
     return 1;
 }

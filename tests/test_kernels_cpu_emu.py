@@ -70,3 +70,8 @@ def test_batched_run_with_zeroed_fresh_memory(checks):
     rc, err = _run(checks, "batch", "12", "0", "0")
     assert rc == 0 and "ALL EQUAL" in err, err[-4000:]
 
+
+
+def test_trajectory_rows_equal_stepwise_estimates(checks):
+    rc, err = _run(checks, "traj")
+    assert rc == 0 and "TRAJ EQUAL" in err, err[-4000:]
