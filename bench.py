@@ -82,21 +82,19 @@ VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 
 def valu_entry(counters, kernel_ms: float, n_particles: int):
     """VALU use of k_step from the counters in profiles/k_step_traffic.json:
-    instructions per particle-step, and the busy fraction from the counted
-    VALU cycles (SQ_ACTIVE_INST_VALU counts the cycles VALU instructions
-    occupy, so quarter-rate and transcendental instructions weigh what they
-    cost) over the SIMD cycles of the kernel's duration."""
+    instructions per particle-step, the instruction classes, and the busy
+    fraction rocprofv3's VALUBusy reports (SQ_ACTIVE_INST_VALU, the cycles
+    VALU instructions occupy -- so quarter-rate and transcendental
+    instructions weigh what they cost -- per CU over GRBM_GUI_ACTIVE)."""
     if not counters or "valu_insts" not in counters:
         return None
     v = {"insts_per_launch": counters["valu_insts"],
          "insts_per_particle_step": counters["valu_insts"] * 64.0 / n_particles,
          "issue_ms_at_4_cycles": counters["valu_insts"] / VALU_WAVE_INSTR_PER_S * 1e3}
-    if "valu_active_cycles" in counters:
-        # SQ_ACTIVE_INST_VALU is summed over the waves; in units of 4 cycles
-        # per SIMD (quad-cycle counter), over 1024 SIMDs at 2.4 GHz
-        busy_s = counters["valu_active_cycles"] * 4.0 / 1024 / 2.4e9
-        v["busy_frac"] = busy_s * 1e3 / kernel_ms
-    for k in ("valu_busy_pct", "valu_by_class", "wait_inst_any"):
+    if "valu_busy_pct" in counters:
+        v["busy_frac"] = counters["valu_busy_pct"] / 100.0
+    for k in ("valu_by_class", "wait_inst_any", "salu_insts", "lds_insts",
+              "lds_bank_conflict_cycles"):
         if k in counters:
             v[k] = counters[k]
     return v
