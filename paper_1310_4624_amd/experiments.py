@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 
 import numpy as np
 
@@ -182,10 +183,69 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
     return out
 
 
+def infoshare_study(seeds: int = 10, modes=("arna", "rna0", "rna10", "rna50"),
+                    n_pe: int = 256, n_per_pe: int = 4096, steps: int = 200,
+                    curve_pes=(24, 96, 192, 384), curve_steps: int = 20,
+                    curve_n_per_pe: int = 4096) -> dict:
+    """The information-sharing result of Sec. V-B / Fig. 3 over several seeds:
+    per mode the iterations until every PE estimate is within 2 px of the spot
+    (None: not within `steps`; the median counts those as later than any
+    converged run), and PE_eff / M after 10 and 20 iterations at the PE counts
+    of Fig. 3.  Seed s uses sequence 1000 + s and filter seed 1 + s for every
+    mode, so the modes see the same frames and start."""
+    runs = {m: [] for m in modes}
+    for s in range(seeds):
+        # the workload's full sequence (200 frames) whatever `steps` is: its
+        # frames do not depend on how many iterations are run
+        seq = synth.make_sequence("arna_infoshare_512_256x4096", seed=1000 + s)
+        for m in modes:
+            r = infoshare(m, seq_seed=1000 + s, filter_seed=1 + s, n_pe=n_pe, n_per_pe=n_per_pe,
+                          steps=steps, seq=seq)
+            print(f"infoshare seed {s} {m}: converged at {r['converged_at']}", file=sys.stderr,
+                  flush=True)
+            runs[m].append(dict(seed=s, converged_at=r["converged_at"],
+                                within_at_10=r["fraction_within"][9],
+                                within_at_20=r["fraction_within"][19],
+                                pe_eff_over_m_at_10=r["pe_eff_over_m"][9],
+                                pe_eff_over_m_at_20=r["pe_eff_over_m"][19]))
+
+    def median_steps(rs):
+        v = sorted(steps + 1 if r["converged_at"] is None else r["converged_at"] for r in rs)
+        med = float(np.median(v))
+        return None if med > steps else med
+
+    summary = {m: dict(median_converged_at=median_steps(rs),
+                       converged_runs=sum(r["converged_at"] is not None for r in rs),
+                       runs=len(rs)) for m, rs in runs.items()}
+    curves = {}
+    cseqs = [synth.make_sequence("arna_infoshare_512_256x4096", seed=1000 + s, frames=curve_steps)
+             for s in range(seeds)]
+    for n in curve_pes:
+        for m in modes:
+            vals = {10: [], 20: []}
+            for s in range(seeds):
+                seq = cseqs[s]
+                r = infoshare(m, seq_seed=1000 + s, filter_seed=1 + s, n_pe=n, n_per_pe=curve_n_per_pe,
+                              steps=curve_steps, seq=seq)
+                for i in vals:
+                    if i <= len(r["pe_eff_over_m"]):
+                        vals[i].append(r["pe_eff_over_m"][i - 1])
+            print(f"PE_eff curves {n} PEs {m} done", file=sys.stderr, flush=True)
+            curves.setdefault(str(n), {})[m] = {
+                f"pe_eff_over_m_at_{i}": dict(median=float(np.median(v)), min=float(min(v)),
+                                              max=float(max(v)))
+                for i, v in vals.items() if v}
+    return dict(experiment="information sharing (Sec. V-B, Fig. 3)", n_pe=n_pe,
+                n_per_pe=n_per_pe, steps=steps, radius_px=2.0, seeds=seeds, summary=summary,
+                runs=runs, pe_eff_curves=dict(n_per_pe=curve_n_per_pe, steps=curve_steps,
+                                              by_pe_count=curves))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling",
-                                     "batch"])
+                                     "batch", "infoshare-study"])
+    ap.add_argument("--out", default="", help="infoshare-study: also write the JSON here")
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
     ap.add_argument("--ring-groups", type=int, default=0)
     ap.add_argument("--modes", default="arna,rna10,rna50,rna0")
@@ -196,6 +256,16 @@ def main():
     ap.add_argument("--curves", action="store_true", help="include the per-step curves")
     args = ap.parse_args()
     out = []
+    if args.what == "infoshare-study":
+        r = infoshare_study(seeds=args.seeds, modes=tuple(args.modes.split(",")),
+                            n_pe=args.n_pe, n_per_pe=args.n_per_pe, steps=args.steps or 200)
+        r["command"] = "python -m paper_1310_4624_amd.experiments " + " ".join(sys.argv[1:])
+        text = json.dumps(r, indent=1)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(text + "\n")
+        print(json.dumps(r["summary"]), flush=True)
+        return
     if args.what == "batch":
         print(json.dumps(batch(frames=args.steps or 20)), flush=True)
         return

@@ -37,12 +37,14 @@ CASES = {
                                            n_per_pe=256), frames=6),
     "arna_2x4096": dict(over=dict(mode=O.MODE_ARNA, n_pe=2, n_per_pe=4096), frames=5),
     "rna_border_3x1000": dict(over=dict(n_pe=3, n_per_pe=1000, width=40, height=40), frames=6),
+    # the differentiable workload's shape: 2^20 particles over 256 PEs, 512 x 512
+    "c5_arna_256x4096": dict(workload="arna_grad_512_256x4096", over={}, frames=12),
 }
 
 
 def _setup(name, seed=3):
     c = CASES[name]
-    wl = "rna_128_4x256"
+    wl = c.get("workload", "rna_128_4x256")
     cfg = synth.filter_config(wl, seed=seed, **c["over"])
     K = c["frames"]
     if "width" in c["over"]:
@@ -87,6 +89,7 @@ def _gpu_run(cfg, truth, frames, tape=None):
 
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_gradient_matches_oracle(name):
+    print(f"case {name}", flush=True)
     cfg, frames, truth = _setup(name)
     J, dJ, tape = O.grad(cfg, truth.astype(np.float64), frames)
     Jv, res = _gpu_run(cfg, truth, frames, tape=tape)
@@ -100,7 +103,9 @@ def test_free_run_choices_mostly_agree():
     rare quantization ties (checked on the first iteration, before any tie
     can change the states)."""
     p = pf()
-    for name in sorted(CASES):
+    # (the small shapes: at 2^20 particles the one-step parity test compares
+    # every ancestor against the oracle with the quantization tolerance)
+    for name in sorted(n for n in CASES if "workload" not in CASES[n]):
         cfg, frames, truth = _setup(name)
         _, _, tape = O.grad(cfg, truth.astype(np.float64), frames[:1])
         tr = p.Tracker(cfg, truth, debug=p.PF_DEBUG_TRACE)

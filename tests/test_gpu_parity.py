@@ -197,23 +197,29 @@ def seeded_case(name):
     return cfg, np.asarray(frame, np.float32), state, logmass
 
 
+def gpu_outputs(g):
+    out = {k: g.debug_get(k) for k in ["ring", "nex", "src", "lam", "prop", "ell", "q",
+                                       "ancestors", "v", "state", "pe_records"]}
+    out["est"] = g.estimate()
+    return out
+
+
+def oracle_step(cfg, frame, state, logmass, k_done):
+    o = orc.Oracle(cfg, np.zeros((cfg["n_filters"], 5), np.float32))
+    o.set_state(state.astype(np.float64), logmass, k_done)
+    o.set_ambiguity(H.AMB_EPS_REL, H.AMB_EPS_ABS)
+    return o.step(frame)
+
+
 def run_one_step(cfg, frame, state, logmass, k_done):
     p = pf()
     F = cfg["n_filters"]
-    truth = np.zeros((F, 5), np.float32)
-    g = p.Tracker(cfg, truth, debug=p.PF_DEBUG_TRACE)
+    g = p.Tracker(cfg, np.zeros((F, 5), np.float32), debug=p.PF_DEBUG_TRACE)
     g.set_state(state, logmass, step=k_done)
     g.step(torch.from_numpy(frame).cuda())
-    est = g.estimate()
-    out = {k: g.debug_get(k) for k in ["ring", "nex", "src", "lam", "prop", "ell", "q",
-                                       "ancestors", "v", "state", "pe_records"]}
-    out["est"] = est
+    out = gpu_outputs(g)
     g.close()
-    o = orc.Oracle(cfg, truth)
-    o.set_state(state.astype(np.float64), logmass, k_done)
-    o.set_ambiguity(H.AMB_EPS_REL, H.AMB_EPS_ABS)
-    tr = o.step(frame)
-    return out, tr
+    return out, oracle_step(cfg, frame, state, logmass, k_done)
 
 
 @pytest.mark.parametrize("name", ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500",
@@ -235,6 +241,38 @@ def check_one_step(name, k_done):
     print(f"one-step parity {name} k_done={k_done}", flush=True)
     cfg, frame, state, logmass = seeded_case(name)
     g, tr = run_one_step(cfg, frame, state, logmass, k_done)
+    compare_one_step(cfg, frame, g, tr, k_done)
+
+
+BATCH_CASES = ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500", "poisson_arna_1x4x1000",
+               "point_rna_3x5x77", "arna_groups_2x24x300"]
+
+
+def test_one_step_parity_batched():
+    """One iteration of a mixed batch (pf_batch_run: contexts of different
+    shapes, likelihoods and kernel variants in shared launches) against the
+    oracle, context by context, with the bar of the single-context test."""
+    p = pf()
+    k_done = 3
+    cases = [seeded_case(n) for n in BATCH_CASES]
+    trs = []
+    for cfg, frame, state, logmass in cases:
+        g = p.Tracker(cfg, np.zeros((cfg["n_filters"], 5), np.float32), debug=p.PF_DEBUG_TRACE)
+        g.set_state(state, logmass, step=k_done)
+        trs.append(g)
+    b = p.Batch(trs)
+    b.run([torch.from_numpy(frame[None]).cuda() for _, frame, _, _ in cases])
+    torch.cuda.synchronize()
+    for name, (cfg, frame, state, logmass), g in zip(BATCH_CASES, cases, trs):
+        print(f"batched one-step parity {name}", flush=True)
+        compare_one_step(cfg, frame, gpu_outputs(g), oracle_step(cfg, frame, state, logmass, k_done),
+                         k_done)
+    b.close()
+    for g in trs:
+        g.close()
+
+
+def compare_one_step(cfg, frame, g, tr, k_done):
     F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
     N = F * M * n_p
     # integer stages of steps 1-3: exact
