@@ -223,10 +223,14 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out);
 
 /* n_steps iterations of every context: context i takes its frames from
  * d_frames[i] + s * frame_stride[i] (host arrays of n device pointers and
- * strides in floats).  use_graph != 0 captures the whole run into one HIP
- * graph, launches it and synchronizes the stream; otherwise the launches are
- * only enqueued (the call still synchronizes once, before uploading the
- * run's argument table).  PF_ESTATE if a context is recording a gradient. */
+ * strides in floats).  use_graph != 0 runs the batched contexts as HIP
+ * graphs, in runs of at most 64 iterations: the launches of a run of a given
+ * length are captured once per batch and replayed (their arguments are read
+ * from the batch's device table, which each run rewrites); the ring tables
+ * are rebuilt ahead of a run when needed, and the contexts without a batched
+ * variant run beside the graph.  Either way the launches are only enqueued
+ * (the call synchronizes the stream before it rewrites the argument table).
+ * PF_ESTATE if a context is recording a gradient. */
 int pf_batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
                  uint32_t n_steps, int use_graph);
 

@@ -133,6 +133,10 @@ struct pf_batch {
     std::vector<hipStream_t> workers;
     hipEvent_t ev_fork;
     std::vector<hipEvent_t> ev_join;
+    // graph mode: the launches of a run of n iterations of the batched groups,
+    // captured once per n and replayed (their arguments are re-read from
+    // d_args, which every run rewrites); dropped when d_args moves
+    std::vector<std::pair<uint32_t, hipGraphExec_t>> graphs;
 };
 
 // Argument table of pf_batch_run_noalloc: a fixed device array, one copy per
@@ -1122,6 +1126,130 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
 
 namespace {
 
+// Graph mode of pf_batch_run, in runs of at most kRingSteps iterations.  The
+// ring tables are rebuilt before a run when they do not cover it (outside the
+// graph), so a run's launches depend only on its length: the graph of the
+// batched groups' launches for a length is captured once and replayed, its
+// arguments re-read from d_args, which every run rewrites.  The contexts
+// launched one by one run beside the graph on a worker stream.
+int batch_run_graph(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
+                    uint32_t n_steps) {
+    const uint32_t nb = b->n_batched;
+    const size_t cap = (size_t)kRingSteps * (nb ? nb : 1);
+    if (b->args_cap < cap) {
+        for (auto &e : b->graphs) (void)hipGraphExecDestroy(e.second);
+        b->graphs.clear();
+        HIP_OK(hipStreamSynchronize(b->stream));
+        if (b->d_args) (void)hipFree(b->d_args);
+        b->d_args = nullptr;
+        b->args_cap = 0;
+        const int rc = dev_alloc(&b->d_args, cap);
+        if (rc != PF_OK) return rc;
+        b->args_cap = cap;
+    }
+    const size_t nw = b->workers.size();
+    for (uint32_t done = 0; done < n_steps;) {
+        const uint32_t n = n_steps - done < kRingSteps ? n_steps - done : kRingSteps;
+        // ring tables covering iterations k0 .. k0 + n - 1 of every batched
+        // context, enqueued before the graph on the batch's stream
+        for (auto &g : b->groups)
+            for (uint32_t i : g.members) {
+                pf_ctx *c = b->ctx[i];
+                if (c->cfg.mode != PF_MODE_ARNA || c->cfg.n_pe <= 1) continue;
+                const uint64_t k0 = c->step + 1;
+                if (c->ring_valid && k0 >= c->ring_base && k0 + n - 1 < c->ring_base + kRingSteps)
+                    continue;
+                c->ring_base = k0;
+                c->ring_valid = true;
+                const int rc = launch_ring(c, k0);
+                if (rc != PF_OK) return rc;
+            }
+        std::vector<StepArgs> args((size_t)n * nb);
+        for (uint32_t t = 0; t < n; ++t) {
+            uint32_t slot = 0;
+            for (auto &g : b->groups)
+                for (uint32_t i : g.members) {
+                    pf_ctx *c = b->ctx[i];
+                    const uint64_t k = c->step + 1;
+                    args[(size_t)t * nb + slot++] =
+                        make_args(c, k, d_frames[i] + (size_t)(done + t) * frame_stride[i]);
+                    advance(c, k);
+                }
+        }
+        HIP_OK(hipStreamSynchronize(b->stream));   // earlier runs may still read d_args
+        if (!args.empty())
+            HIP_OK(hipMemcpy(b->d_args, args.data(), args.size() * sizeof(StepArgs),
+                             hipMemcpyHostToDevice));
+        hipGraphExec_t exec = nullptr;
+        for (auto &e : b->graphs)
+            if (e.first == n) exec = e.second;
+        if (!exec && !b->groups.empty()) {
+            // capture: a private stream forks to the workers, each group's n
+            // launches on its worker, joined back
+            hipStream_t cap_st = nullptr;
+            HIP_OK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+            int rc = PF_OK;
+            if (hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) rc = PF_EHIP;
+            if (rc == PF_OK && hipEventRecord(b->ev_fork, cap_st) != hipSuccess) rc = PF_EHIP;
+            for (size_t w = 0; w < nw && rc == PF_OK; ++w)
+                if (hipStreamWaitEvent(b->workers[w], b->ev_fork, 0) != hipSuccess) rc = PF_EHIP;
+            for (uint32_t t = 0; t < n && rc == PF_OK; ++t) {
+                uint32_t slot = 0;
+                for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+                    auto &g = b->groups[gi];
+                    const StepArgs *ga = b->d_args + (size_t)t * nb + slot;
+                    uint32_t cnt = (uint32_t)g.members.size();
+                    void *kargs[] = {&ga, &g.d_first, &cnt};
+                    if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds,
+                                        b->workers[gi % nw]) != hipSuccess) {
+                        rc = PF_EHIP;
+                        break;
+                    }
+                    slot += cnt;
+                }
+            }
+            for (size_t w = 0; w < nw; ++w)
+                if (hipEventRecord(b->ev_join[w], b->workers[w]) != hipSuccess ||
+                    hipStreamWaitEvent(cap_st, b->ev_join[w], 0) != hipSuccess)
+                    rc = PF_EHIP;
+            hipGraph_t graph = nullptr;
+            if (hipStreamEndCapture(cap_st, &graph) != hipSuccess) rc = PF_EHIP;
+            if (rc == PF_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                exec = nullptr;
+                rc = PF_EHIP;
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipStreamDestroy(cap_st);
+            if (rc != PF_OK) {
+                (void)hipGetLastError();
+                return rc;
+            }
+            b->graphs.push_back({n, exec});
+        }
+        if (exec) HIP_OK(hipGraphLaunch(exec, b->stream));
+        // the contexts without a batched variant, beside the graph
+        if (!b->solo.empty()) {
+            hipStream_t w = b->workers[0];
+            HIP_OK(hipEventRecord(b->ev_fork, b->stream));
+            HIP_OK(hipStreamWaitEvent(w, b->ev_fork, 0));
+            int rc = PF_OK;
+            for (uint32_t i : b->solo) {
+                pf_ctx *c = b->ctx[i];
+                c->stream = w;
+                for (uint32_t t = 0; t < n && rc == PF_OK; ++t)
+                    rc = launch_step(c, d_frames[i] + (size_t)(done + t) * frame_stride[i]);
+                c->stream = b->stream;
+            }
+            if (hipEventRecord(b->ev_join[0], w) != hipSuccess ||
+                hipStreamWaitEvent(b->stream, b->ev_join[0], 0) != hipSuccess)
+                rc = PF_EHIP;
+            if (rc != PF_OK) return rc;
+        }
+        done += n;
+    }
+    return PF_OK;
+}
+
 // pf_batch_run; with `fixed` (cap entries) the argument table goes there
 // instead of the batch's own buffer, and nothing is allocated on the device.
 int batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_stride,
@@ -1136,6 +1264,7 @@ int batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_s
     if (n_steps == 0) return PF_OK;
     const uint32_t nb = b->n_batched;
     if (fixed && (uint64_t)n_steps * nb > fixed_cap) return PF_EUNSUPPORTED;
+    if (use_graph && !fixed) return batch_run_graph(b, d_frames, frame_stride, n_steps);
     // host pass: every batched context's arguments for every iteration, and
     // the ring tables each iteration has to rebuild first (rings[i]: context,
     // first iteration of the new table)
@@ -1181,6 +1310,9 @@ int batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_s
     };
     restore();
     if (!fixed && b->args_cap < args.size()) {
+        for (auto &e : b->graphs) (void)hipGraphExecDestroy(e.second);
+        b->graphs.clear();
+        HIP_OK(hipStreamSynchronize(b->stream));
         if (b->d_args) (void)hipFree(b->d_args);
         b->d_args = nullptr;
         b->args_cap = 0;
@@ -1299,6 +1431,7 @@ void pf_batch_destroy(pf_batch *b) {
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (auto &g : b->groups)
         if (g.d_first) (void)hipFree(g.d_first);
+    for (auto &e : b->graphs) (void)hipGraphExecDestroy(e.second);
     if (b->d_args) (void)hipFree(b->d_args);
     delete b;
 }

@@ -111,19 +111,24 @@ def scaling(mode: str, n_pe: int, total: int = 1 << 20, steps: int = 30, warmup:
                 us_per_step=float(ms[~ring].mean() * 1e3), n_ex=int(est["n_ex"][0]))
 
 
-def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000) -> dict:
+def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000,
+          call: int = 5) -> dict:
     """The batched workload: n_seq independent sequences of uneven size run
     (a) one after another, one launch per sequence and iteration, (b) as one
-    batch (one launch per kernel variant and iteration), (c) the batch as one
-    HIP graph (captured and instantiated inside the timed region), (d) (b) and
-    (c) with the workgroup sizes chosen by the autotuner.
+    batch (one launch per kernel variant and iteration), (c) the batch as HIP
+    graphs, (d) (b) and (c) with the workgroup sizes chosen by the autotuner.
+    Like a serving loop, (b) and (c) take the frames in calls of `call`
+    iterations: the first call (untimed) loads the kernels and, in (c),
+    captures the graph of a `call`-iteration run, which the timed calls
+    replay.  Every mode times the same frames (all but the first `call`).
     Throughput = total particle-steps / time between two events."""
     import torch
     from . import autotune
     from .tracker import Batch
     seqs = synth.batch_sequences(seed=seed, n_seq=n_seq, frames=frames)
     dev = [torch.from_numpy(fr).cuda() for _, _, fr in seqs]
-    total = sum(c["n_filters"] * c["n_pe"] * c["n_per_pe"] for c, _, _ in seqs) * frames
+    timed_frames = frames - call
+    total = sum(c["n_filters"] * c["n_pe"] * c["n_per_pe"] for c, _, _ in seqs) * timed_frames
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -139,42 +144,43 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
         return [Tracker(dict(c, block_size=(block_sizes[i] if block_sizes else 0)), t)
                 for i, (c, t, _) in enumerate(seqs)]
 
-    out = {"n_seq": n_seq, "frames": frames, "particle_steps": total}
-    # warm-up: load every kernel variant once, batched and per context (two
-    # iterations, so that multi-iteration launches are loaded too)
-    trs = make()
-    Batch(trs).run([d[:1] for d in dev])
-    for t in trs:
-        t.close()
+    def batched(block_sizes, graph):
+        trs = make(block_sizes)
+        b = Batch(trs)
+        b.run([d[:call] for d in dev], graph=graph)
+        ms = timed(lambda: [b.run([d[t0:t0 + call] for d in dev], graph=graph)
+                            for t0 in range(call, frames, call)])
+        x = [t.estimate()["x_global"] for t in trs]
+        b.close()
+        for t in trs:
+            t.close()
+        return ms, x
+
+    out = {"n_seq": n_seq, "frames": frames, "frames_per_call": call,
+           "timed_frames": timed_frames, "particle_steps": total}
+    # warm-up: load every kernel variant once, per context (two iterations,
+    # so that multi-iteration launches are loaded too)
     trs = make()
     for t, d in zip(trs, dev):
         t.run(d[:2])
     for t in trs:
         t.close()
     trs = make()
-    ms = timed(lambda: [t.run(d) for t, d in zip(trs, dev)])
+    for t, d in zip(trs, dev):
+        t.run(d[:call])
+    ms = timed(lambda: [t.run(d[call:]) for t, d in zip(trs, dev)])
     ref = [t.estimate()["x_global"] for t in trs]
     for t in trs:
         t.close()
     out["sequential_ms"] = ms
     for name, graph in (("batched_ms", False), ("batched_graph_ms", True)):
-        trs = make()
-        b = Batch(trs)
-        out[name] = timed(lambda: b.run(dev, graph=graph))
-        out[name.replace("_ms", "_equal")] = all(
-            np.array_equal(t.estimate()["x_global"], r) for t, r in zip(trs, ref))
-        b.close()
-        for t in trs:
-            t.close()
+        ms, x = batched(None, graph)
+        out[name] = ms
+        out[name.replace("_ms", "_equal")] = all(np.array_equal(a, r) for a, r in zip(x, ref))
     if tune:
         blocks = [autotune.tune(c, t, d, steps=min(6, frames - 2)) for (c, t, _), d in zip(seqs, dev)]
         for name, graph in (("batched_tuned_ms", False), ("batched_graph_tuned_ms", True)):
-            trs = make(blocks)
-            b = Batch(trs)
-            out[name] = timed(lambda: b.run(dev, graph=graph))
-            b.close()
-            for t in trs:
-                t.close()
+            out[name], _ = batched(blocks, graph)
         out["tuned_block_sizes"] = blocks
         out["default_block_sizes"] = [min(1024, (c["n_per_pe"] + 63) // 64 * 64) for c, _, _ in seqs]
     for k in list(out):

@@ -1,8 +1,9 @@
 // Checks of the HIP library run on the CPU under the emulation in
 // emu_rt.cpp, built with AddressSanitizer and UndefinedBehaviorSanitizer:
 //   batch K MODE   nine contexts stepped alone and then together through
-//                  pf_batch_run (MODE 0), its graph mode (1) or
-//                  pf_batch_run_noalloc (2); results compared bit for bit
+//                  pf_batch_run (MODE 0), its graph mode (1; 3: in runs of 10
+//                  iterations, one graph replayed) or pf_batch_run_noalloc
+//                  (2); results compared bit for bit
 //   traj           pf_run_traj's rows against pf_estimate after each step
 #include "src/arna.hip"
 #include <random>
@@ -157,7 +158,13 @@ static int batch_main(int K, int graph) {
         p1.push_back(dfr[i] + split * ins[i].stride);
         strides.push_back(ins[i].stride);
     }
-    if (graph == 2) {   // the entry point that allocates nothing
+    if (graph == 3) {   // graph mode in equal runs: one capture, replayed
+        for (int t0 = 0; t0 < K; t0 += 10) {
+            std::vector<const float *> pt;
+            for (size_t i = 0; i < cases.size(); ++i) pt.push_back(dfr[i] + t0 * ins[i].stride);
+            check(pf_batch_run(b, pt.data(), strides.data(), K - t0 < 10 ? K - t0 : 10, 1), "graph run");
+        }
+    } else if (graph == 2) {   // the entry point that allocates nothing
         const int big = pf_batch_run_noalloc(b, p0.data(), strides.data(), 100000);
         fprintf(stderr, "oversized no-alloc run: %d\n", big);
         if (big != PF_EUNSUPPORTED) return 3;

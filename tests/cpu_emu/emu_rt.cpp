@@ -83,7 +83,15 @@ struct Worker {
 };
 thread_local Worker *tw = nullptr;
 std::mutex g_mu;
-std::map<const void *, EmuInvoker> &reg() { static std::map<const void *, EmuInvoker> r; return r; }
+std::map<const void *, EmuBinder> &reg() { static std::map<const void *, EmuBinder> r; return r; }
+struct Recorded {
+    const void *fn;
+    dim3 g, b;
+    size_t lds;
+    std::function<void()> body;
+};
+bool g_capturing = false;
+std::vector<Recorded> g_record;
 std::map<const void *, int> &attr() { static std::map<const void *, int> a; return a; }
 thread_local hipError_t last_err = hipSuccess;
 std::vector<Worker *> g_workers;
@@ -324,7 +332,15 @@ uint64_t wall_clock64() {
     return (uint64_t)std::chrono::steady_clock::now().time_since_epoch().count() / 10;
 }
 
-void emu_register_invoker(const void *fn, EmuInvoker inv) { reg()[fn] = std::move(inv); }
+void emu_register_binder(const void *fn, EmuBinder bind) { reg()[fn] = std::move(bind); }
+
+hipError_t emu_launch(const void *fn, dim3 g, dim3 b, size_t lds, std::function<void()> body) {
+    if (g_capturing) {
+        g_record.push_back(Recorded{fn, g, b, lds, std::move(body)});
+        return hipSuccess;
+    }
+    return emu_run_grid(fn, g, b, lds, body);
+}
 
 hipError_t emu_run_grid(const void *fn, dim3 g, dim3 b, size_t lds, const std::function<void()> &body) {
     const uint32_t B = b.x * b.y * b.z;
@@ -384,12 +400,30 @@ hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t) new char[1]; return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t s) { delete[](char *) s; return hipSuccess; }
 hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
-hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
-hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) { *g = (hipGraph_t) new char[1]; return hipSuccess; }
-hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, void *, char *, size_t) { *e = (hipGraphExec_t) new char[1]; return hipSuccess; }
-hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
-hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete[](char *) e; return hipSuccess; }
-hipError_t hipGraphDestroy(hipGraph_t g) { delete[](char *) g; return hipSuccess; }
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) {
+    g_capturing = true;
+    g_record.clear();
+    return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+    g_capturing = false;
+    *g = (hipGraph_t) new std::vector<Recorded>(std::move(g_record));
+    g_record.clear();
+    return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t g, void *, char *, size_t) {
+    *e = (hipGraphExec_t) new std::vector<Recorded>(*(std::vector<Recorded> *)g);
+    return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+    for (const Recorded &r : *(std::vector<Recorded> *)e) {
+        const hipError_t rc = emu_run_grid(r.fn, r.g, r.b, r.lds, r.body);
+        if (rc != hipSuccess) return rc;
+    }
+    return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete (std::vector<Recorded> *)e; return hipSuccess; }
+hipError_t hipGraphDestroy(hipGraph_t g) { delete (std::vector<Recorded> *)g; return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t *e) { *e = (hipEvent_t) new char[1]; return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
 hipError_t hipEventDestroy(hipEvent_t e) { delete[](char *) e; return hipSuccess; }
@@ -407,8 +441,7 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *, in
 hipError_t hipLaunchKernel(const void *f, dim3 g, dim3 b, void **args, size_t lds, hipStream_t) {
     auto it = reg().find(f);
     if (it == reg().end()) { fprintf(stderr, "EMU: kernel %p not registered\n", f); abort(); }
-    const EmuInvoker &inv = it->second;
-    return emu_run_grid(f, g, b, lds, [&]() { inv(args); });
+    return emu_launch(f, g, b, lds, it->second(args));
 }
 hipError_t hipLaunchCooperativeKernel(const void *, dim3, dim3, void **, unsigned, hipStream_t) { return hipErrorNotSupported; }
 hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = (void *)sym; return hipSuccess; }

@@ -150,21 +150,27 @@ hipError_t hipGetSymbolAddress(void **p, const void *sym);
 #define HIP_SYMBOL(x) ((const void *)&(x))
 template <class T> static inline hipError_t hipFuncSetAttribute(T *f, hipFuncAttribute a, int v) { return hipFuncSetAttribute((const void *)f, a, v); }
 
-// grid execution: body() runs once per thread of every block
+// grid execution: body() runs once per thread of every block.  While a
+// stream capture is open every launch is recorded (with copies of its
+// arguments) instead, and a graph launch runs the recorded launches in order.
 hipError_t emu_run_grid(const void *fn, dim3 g, dim3 b, size_t lds, const std::function<void()> &body);
-typedef std::function<void(void **)> EmuInvoker;
-void emu_register_invoker(const void *fn, EmuInvoker inv);
+hipError_t emu_launch(const void *fn, dim3 g, dim3 b, size_t lds, std::function<void()> body);
+// binds copies of a launch's arguments (given as hipLaunchKernel's void **)
+typedef std::function<std::function<void()>(void **)> EmuBinder;
+void emu_register_binder(const void *fn, EmuBinder bind);
 template <class... P, size_t... I>
-static inline void emu_invoke(void (*k)(P...), void **a, std::index_sequence<I...>) {
-    k(*(std::remove_cv_t<std::remove_reference_t<P>> *)a[I]...);
+static inline std::function<void()> emu_bind(void (*k)(P...), void **a, std::index_sequence<I...>) {
+    std::tuple<std::remove_cv_t<std::remove_reference_t<P>>...> t(
+        *(std::remove_cv_t<std::remove_reference_t<P>> *)a[I]...);
+    return [k, t]() { std::apply(k, t); };
 }
 template <class... P> static inline void emu_register(void (*k)(P...)) {
-    emu_register_invoker((const void *)k, [k](void **a) { emu_invoke(k, a, std::index_sequence_for<P...>{}); });
+    emu_register_binder((const void *)k, [k](void **a) { return emu_bind(k, a, std::index_sequence_for<P...>{}); });
 }
 template <class... P, class... A>
 static inline hipError_t emu_launch_ggl(void (*k)(P...), dim3 g, dim3 b, size_t lds, hipStream_t, A... a) {
     std::tuple<std::remove_cv_t<std::remove_reference_t<P>>...> t(a...);
-    return emu_run_grid((const void *)k, g, b, lds, [&]() { std::apply(k, t); });
+    return emu_launch((const void *)k, g, b, lds, [k, t]() { std::apply(k, t); });
 }
 #define hipLaunchKernelGGL(k, g, b, lds, s, ...) emu_launch_ggl(k, dim3(g), dim3(b), lds, s, ##__VA_ARGS__)
 template <class... P> static inline void *emu_reg_ret(void (*k)(P...)) { emu_register(k); return (void *)k; }

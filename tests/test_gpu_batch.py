@@ -59,7 +59,7 @@ def _inputs(cfg, K, rng):
     return truth, np.stack(frames)
 
 
-@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("graph", [False, True, "replay"])
 def test_batch_equals_separate_runs(graph):
     import paper_1310_4624_amd as p
     rng = np.random.Generator(np.random.PCG64(2024))
@@ -80,8 +80,12 @@ def test_batch_equals_separate_runs(graph):
     trs = [p.Tracker(c, truth) for c, (truth, _) in zip(cases, inputs)]
     b = p.Batch(trs)
     print(f"batch run (graph={graph})", flush=True)
-    b.run([f[:40] for f in frames], graph=graph)
-    b.run([f[40:K] for f in frames], graph=graph)
+    if graph == "replay":   # runs of 10 iterations: one graph captured, replayed
+        for t0 in range(0, K, 10):
+            b.run([f[t0:t0 + 10] for f in frames], graph=True)
+    else:
+        b.run([f[:40] for f in frames], graph=graph)
+        b.run([f[40:K] for f in frames], graph=graph)
     torch.cuda.synchronize()
     print("batch run done", flush=True)
     for t, (st, rec, est) in zip(trs, solo):

@@ -59,7 +59,7 @@ def _run(exe, *args):
     return res.returncode, res.stderr
 
 
-@pytest.mark.parametrize("mode", ["0", "1", "2"])
+@pytest.mark.parametrize("mode", ["0", "1", "2", "3"])
 def test_batched_run_in_bounds_and_equal_to_separate_runs(checks, mode):
     # 70 iterations cross the ring-table rebuild at iteration 65
     rc, err = _run(checks, "batch", "70", mode)
