@@ -61,7 +61,15 @@ enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the
 
 /* Limits of this build. */
 #define PF_MAX_PE 8192u
-#define PF_MAX_PER_PE 4096u
+#define PF_MAX_PER_PE 65536u
+/* Up to this many particles per PE a PE's particles live in LDS for the whole
+ * iteration.  Larger PEs stream them through HBM (a second step kernel with the
+ * same results up to the summation order of the FP64 PE sums): such contexts
+ * take no block_size other than 0 or 1024, no PF_DEBUG_LINEAGE, no
+ * PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no gradient recording
+ * (PF_EUNSUPPORTED), run in a batch one by one, and hold N more floats of
+ * device memory (the log-weights of the iteration). */
+#define PF_MAX_PER_PE_LDS 4096u
 #define PF_MAX_PATCH 15u
 #define PF_MAX_PARTICLES (1u << 29)   /* F M N_p: state indices are 32-bit (5 F M N_p < 2^32) */
 
@@ -103,7 +111,8 @@ typedef struct {
                                  * default (N_p rounded up to 64, at most 1024); else a
                                  * multiple of 64 in 64..1024 with block_size * P >= N_p
                                  * for P = 1, 2 or 4 slots per thread (the smallest such P
-                                 * is used) -- the knob of the autotuner */
+                                 * is used) -- the knob of the autotuner.  Above
+                                 * PF_MAX_PER_PE_LDS particles per PE: 0 or 1024 */
     uint32_t launch;            /* PF_LAUNCH_*.  A multi-iteration launch runs up to 64
                                  * iterations with every PE's workgroup resident on its
                                  * compute unit: its resampled particles stay in registers,
@@ -267,7 +276,8 @@ void pf_batch_destroy(pf_batch *b);
  * pf_grad_begin starts recording: the next max_steps iterations (pf_step /
  * pf_run) keep their propagated particles, ancestors and PE records on the
  * device ((max_steps + 1) x (22 N + 56 F M) bytes, kept for reuse until
- * pf_destroy).  Patch likelihood only (PF_EUNSUPPORTED otherwise); q must be
+ * pf_destroy).  Patch likelihood and N_p <= PF_MAX_PER_PE_LDS only
+ * (PF_EUNSUPPORTED otherwise); q must be
  * positive (PF_EINVAL).  PF_ESTATE while recording or after pf_exchange.
  * An iteration beyond max_steps returns PF_ESTATE and does nothing. */
 int pf_grad_begin(pf_ctx *c, uint32_t max_steps);
@@ -330,7 +340,8 @@ int pf_debug_force_next(pf_ctx *c, const uint32_t *d_anc, const uint32_t *d_nex)
 
 /* The device integer stages on host arrays, run synchronously on the current
  * device with the same device code as pf_step. */
-/* Systematic resampling (Alg. 3, step 7) of n_blocks independent PEs:
+/* Systematic resampling (Alg. 3, step 7) of n_blocks independent PEs of
+ * n_p <= PF_MAX_PER_PE_LDS particles (the LDS kernel's stage):
  * q [n_blocks][n_p] fixed-point weights, v [n_blocks] offsets (v < sum q),
  * anc_out [n_blocks][n_p] ancestors a_j = min{i : n_p C_i > j T + v}. */
 int pf_debug_resample_q(const uint32_t *q, uint32_t n_blocks, uint32_t n_p, const uint32_t *v,

@@ -19,7 +19,8 @@ PF_INIT_TRACKING, PF_INIT_INFOSHARE = 0, 1
 PF_LIK_PATCH, PF_LIK_POINT, PF_LIK_POISSON = 0, 1, 2
 PF_LAUNCH_AUTO, PF_LAUNCH_STEPWISE, PF_LAUNCH_PERSISTENT = 0, 1, 2
 PF_DEBUG_TRACE, PF_DEBUG_LINEAGE = 1, 2
-PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 4096, 15
+PF_MAX_PE, PF_MAX_PER_PE, PF_MAX_PATCH = 8192, 65536, 15
+PF_MAX_PER_PE_LDS = 4096
 PF_MAX_PARTICLES = 1 << 29
 PF_BATCH_NOALLOC_MAX_ARGS = 4096
 

@@ -14,6 +14,7 @@ import os
 
 import numpy as np
 
+from . import _native as nat
 from .tracker import Tracker
 
 _CACHE: dict = {}
@@ -22,7 +23,10 @@ _CACHE: dict = {}
 def candidates(n_p: int) -> list:
     """Workgroup sizes worth timing for N_p particles per PE: the powers of two
     from 64 and N_p rounded up to 64, at most that and 1024, and large
-    enough that 4 slots per thread cover N_p."""
+    enough that 4 slots per thread cover N_p (PEs beyond the LDS stage: the
+    streaming kernel's 1024 only)."""
+    if n_p > nat.PF_MAX_PER_PE_LDS:
+        return [1024]
     top = min(1024, (n_p + 63) // 64 * 64)
     sizes = {b for b in (64, 128, 256, 512, 1024) if b <= top} | {top}
     return sorted(b for b in sizes if 4 * b >= n_p)

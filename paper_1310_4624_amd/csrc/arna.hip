@@ -30,6 +30,7 @@
 #include "arna_device.hpp"
 #include "arna_kernels.hpp"
 #include "arna_adjoint.hpp"
+#include "arna_stream.hpp"
 
 using namespace arna;
 
@@ -66,6 +67,9 @@ struct pf_ctx {
     uint64_t N, FM;
     uint32_t block, ppt, half;
     size_t lds;
+    // N_p > PF_MAX_PER_PE_LDS: the streaming step kernel and its log-weights
+    bool streamk;
+    float *u;                      // [N]
     float *prop[2];
     uint16_t *anc[2];
     pf_pe_record *rec[2];
@@ -234,6 +238,38 @@ void *pick_step_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
     return pick_patch_kernel<kLikGauss>(ppt, half);
 }
 
+template <int HALF, int LIK>
+void *stream_kernel() {
+    return reinterpret_cast<void *>(&k_step_stream<HALF, LIK>);
+}
+
+template <int LIK>
+void *pick_stream_patch_kernel(uint32_t half) {
+    switch (half) {
+        case 0: return stream_kernel<0, LIK>();
+        case 1: return stream_kernel<1, LIK>();
+        case 2: return stream_kernel<2, LIK>();
+        case 3: return stream_kernel<3, LIK>();
+        case 4: return stream_kernel<4, LIK>();
+        case 5: return stream_kernel<5, LIK>();
+        case 6: return stream_kernel<6, LIK>();
+        case 7: return stream_kernel<7, LIK>();
+        default: return nullptr;
+    }
+}
+
+void *pick_stream_kernel(uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT) return stream_kernel<0, kLikPoint>();
+    if (lik_mode == PF_LIK_POISSON) return pick_stream_patch_kernel<kLikPoisson>(half);
+    return pick_stream_patch_kernel<kLikGauss>(half);
+}
+
+// The one-iteration kernel of a context.
+void *ctx_step_kernel(const pf_ctx *c) {
+    return c->streamk ? pick_stream_kernel(c->half, c->cfg.lik_mode)
+                      : pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
+}
+
 // Batched variants exist for the paper's 9 x 9 patch (Gaussian or Poisson
 // noise) and for point observations; other contexts of a batch are launched
 // one by one.
@@ -295,7 +331,14 @@ int validate(const pf_config *c) {
     if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
     if (c->ring_groups > 256) return PF_EINVAL;
     if (c->launch > PF_LAUNCH_PERSISTENT) return PF_EINVAL;
-    if (c->block_size) {
+    if (c->n_per_pe > PF_MAX_PER_PE_LDS) {
+        // the streaming kernel: 1024 threads, no lineage tags, no multi-iteration
+        // launch, no once-per-filter master record
+        if (c->block_size && c->block_size != kStreamBlock) return PF_EINVAL;
+        if ((c->debug & PF_DEBUG_LINEAGE) || c->launch == PF_LAUNCH_PERSISTENT ||
+            c->n_pe >= kMasterMinPE)
+            return PF_EUNSUPPORTED;
+    } else if (c->block_size) {
         if (c->block_size % 64 || c->block_size > 1024) return PF_EINVAL;
         if ((uint64_t)c->block_size * 4 < c->n_per_pe) return PF_EINVAL;
     }
@@ -327,7 +370,7 @@ void free_all(pf_ctx *c) {
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
                     c->mrec[0], c->mrec[1], c->arrive, c->bar, c->run_args,
                     c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
-                    c->g_lbar[1], c->g_theta, c->g_out};
+                    c->g_lbar[1], c->g_theta, c->g_out, c->u};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -442,9 +485,9 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
     int rc = ensure_ring(c, k);
     if (rc != PF_OK) return rc;
     StepArgs a = make_args(c, k, frame, traj_prev);
-    void *fn = pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
+    void *fn = ctx_step_kernel(c);
     if (!fn) return PF_EUNSUPPORTED;
-    void *args[] = {&a};
+    void *args[] = {&a, &c->u};   // (the LDS kernel takes the first only)
     HIP_OK(hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(c->block), args, c->lds, c->stream));
     advance(c, k);
     return PF_OK;
@@ -639,7 +682,11 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     const uint32_t F = cfg->n_filters, M = cfg->n_pe, np = cfg->n_per_pe;
     c->FM = (uint64_t)F * M;
     c->N = c->FM * np;
-    if (cfg->block_size) {
+    c->streamk = np > PF_MAX_PER_PE_LDS;
+    if (c->streamk) {
+        c->block = kStreamBlock;
+        c->ppt = 0;
+    } else if (cfg->block_size) {
         c->block = cfg->block_size;
         c->ppt = np <= c->block ? 1 : (np <= 2 * c->block ? 2 : 4);
     } else {
@@ -649,7 +696,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->half = cfg->lik_mode != PF_LIK_POINT ? cfg->patch / 2 : 0;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
-    c->lds = step_lds(np, lineage);
+    c->lds = c->streamk ? stream_lds_bytes() : step_lds(np, lineage);
     c->key0 = (uint32_t)cfg->seed;
     c->key1 = (uint32_t)(cfg->seed >> 32);
     c->fixed_nex = fixed_count(cfg->fixed_ratio, np);
@@ -687,6 +734,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     if (rc == PF_OK) rc = dev_alloc(&c->err, 1);
     if (rc == PF_OK) rc = dev_alloc(&c->nex_used, F);
     if (rc == PF_OK) rc = dev_alloc(&c->est, F);
+    if (rc == PF_OK && c->streamk) rc = dev_alloc(&c->u, N);
     if (rc == PF_OK && trace) {
         rc = dev_alloc(&c->t_pred, c->FM);
         if (rc == PF_OK) rc = dev_alloc(&c->t_v, c->FM);
@@ -716,7 +764,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     float *d_truth = nullptr;
     if (rc == PF_OK) rc = dev_alloc(&d_truth, 5 * (size_t)F);
     if (rc == PF_OK) {
-        void *fn = pick_step_kernel(c->ppt, c->half, cfg->lik_mode);
+        void *fn = ctx_step_kernel(c);
         if (!fn ||
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds) !=
                 hipSuccess)
@@ -888,7 +936,7 @@ void pf_destroy(pf_ctx *c) {
 
 int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
     if (!c || max_steps == 0) return PF_EINVAL;
-    if (c->cfg.lik_mode != PF_LIK_PATCH) return PF_EUNSUPPORTED;
+    if (c->cfg.lik_mode != PF_LIK_PATCH || c->streamk) return PF_EUNSUPPORTED;
     if (!(c->cfg.q > 0.f)) return PF_EINVAL;
     if (c->g_cap || c->exchanged) return PF_ESTATE;
     const uint64_t N = c->N, FM = c->FM;
@@ -1060,7 +1108,7 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
     b->args_cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
         pf_ctx *c = ctxs[i];
-        void *fn = pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
+        void *fn = c->streamk ? nullptr : pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
         if (!fn || c->FM > 0xFFFFFFFFull) {
             b->solo.push_back(i);
             continue;
@@ -1561,7 +1609,7 @@ int pf_debug_set_lineage(pf_ctx *c, const int32_t *tags) {
 
 int pf_debug_resample_q(const uint32_t *q, uint32_t n_blocks, uint32_t n_p, const uint32_t *v,
                         uint32_t *anc_out) {
-    if (!q || !v || !anc_out || n_p == 0 || n_p > PF_MAX_PER_PE) return PF_EINVAL;
+    if (!q || !v || !anc_out || n_p == 0 || n_p > PF_MAX_PER_PE_LDS) return PF_EINVAL;
     if (n_blocks == 0) return PF_OK;
     const size_t n = (size_t)n_blocks * n_p;
     for (uint32_t b = 0; b < n_blocks; ++b) {   // reject what the kernel cannot take

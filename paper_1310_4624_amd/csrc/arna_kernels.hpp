@@ -291,13 +291,14 @@ __device__ __forceinline__ bool map_by_wave0(uint32_t nex, uint32_t M) {
 
 // Step 3 for one slot: if slot s of PE m is refilled (s = s_t(m) for some
 // t < N_ex), the slot s_t(pred(m)) of pred's resampled block it receives;
-// else 0xFFFF.  The t with floor((t N_p + c_own) / N_ex) = s is the least
+// else kNoSlot.  The t with floor((t N_p + c_own) / N_ex) = s is the least
 // t >= (s N_ex - c_own) / N_p (at most one: N_ex <= N_p).
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 __device__ __forceinline__ uint32_t received_from(uint32_t s, const Prologue &p, uint32_t np) {
-    if (p.nex == 0) return 0xFFFFu;
+    if (p.nex == 0) return kNoSlot;
     const int64_t num = (int64_t)s * p.nex - (int64_t)p.c_own;
     const uint64_t t = num <= 0 ? 0u : (uint64_t)((num + np - 1) / np);
-    if (t >= p.nex || (t * np + p.c_own) / p.nex != s) return 0xFFFFu;
+    if (t >= p.nex || (t * np + p.c_own) / p.nex != s) return kNoSlot;
     return (uint32_t)((t * np + p.c_pred) / p.nex);
 }
 
@@ -1176,20 +1177,24 @@ __global__ __launch_bounds__(64) void k_global_wave(const pf_pe_record *rec, pf_
     }
 }
 
-// pf_exchange: steps 1-3 of the next iteration, exported as a source map.
+// pf_exchange: steps 1-3 of the next iteration, exported as a source map
+// (the receive map in LDS up to PF_MAX_PER_PE_LDS slots, else slot by slot).
 __global__ __launch_bounds__(256) void k_exchange_map(StepArgs a, int64_t *src) {
     __shared__ Prologue pro;
-    __shared__ uint16_t recv[PF_MAX_PER_PE];
+    __shared__ uint16_t recv[PF_MAX_PER_PE_LDS];
     const uint32_t f = blockIdx.x / a.M, m = blockIdx.x % a.M;
+    const bool lds_map = a.np <= PF_MAX_PER_PE_LDS;
     if (threadIdx.x < kWave) prologue_wave(a, f, m, &pro, threadIdx.x);
-    for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) recv[s] = 0xFFFF;
+    if (lds_map)
+        for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) recv[s] = 0xFFFF;
     __syncthreads();
     const Prologue p = pro;
-    build_receive_map(recv, p, a.np, threadIdx.x);
+    if (lds_map) build_receive_map(recv, p, a.np, threadIdx.x);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < a.np; s += blockDim.x) {
-        const uint32_t r = recv[s];
-        const uint64_t g = (r == 0xFFFFu) ? (uint64_t)blockIdx.x * a.np + s
+        const uint32_t r = lds_map ? (recv[s] == 0xFFFFu ? kNoSlot : recv[s])
+                                   : received_from(s, p, a.np);
+        const uint64_t g = (r == kNoSlot) ? (uint64_t)blockIdx.x * a.np + s
                                           : ((uint64_t)f * a.M + p.pred) * a.np + r;
         src[(uint64_t)blockIdx.x * a.np + s] = (int64_t)g;
     }
@@ -1200,7 +1205,7 @@ template <int PPT>
 __global__ __launch_bounds__(1024) void k_resample_q(const uint32_t *q, const uint32_t *v,
                                                      uint32_t *anc_out, uint32_t np) {
     __shared__ uint32_t wq[kMaxWaves * 4];
-    __shared__ uint32_t mark[PF_MAX_PER_PE];
+    __shared__ uint32_t mark[PF_MAX_PER_PE_LDS];
     const uint32_t base = blockIdx.x * np;
     uint32_t Qv[PPT], cinc[PPT], anc[PPT];
 #pragma unroll

@@ -241,9 +241,10 @@ def render_windowed(truth_k, width, height, psf_sigma, background, noise_sigma, 
 def batch_sequences(seed: int = 2000, n_seq: int = 64, frames: int = 50):
     """Independent tracking problems of uneven size for the batched launch:
     frames of 256^2, 512^2 or 1024^2, 1-3 spots of SNR 2-8 (one filter per
-    spot), 2^14..2^20 particles (log-uniform) over 16..256 PEs (log-uniform);
-    N_p = N / (F M) is kept within 64..4096 (the LDS bound of one PE) by
-    moving M.  Returns [(cfg, truth [F][5] float32, frames [K][H][W])]."""
+    spot), 2^14..2^20 particles (log-uniform) over 16..256 PEs (log-uniform),
+    so N_p = N / (F M) spans 64..65536 (at least 64; PEs above 4096 particles
+    run the streaming step).  Returns [(cfg, truth [F][5] float32, frames
+    [K][H][W])]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for i in range(n_seq):
@@ -252,9 +253,6 @@ def batch_sequences(seed: int = 2000, n_seq: int = 64, frames: int = 50):
         N = int(round(2 ** rng.uniform(14, 20)))
         M = int(round(2 ** rng.uniform(4, 8)))
         n_p = max(64, N // (F * M))
-        while n_p > 4096:
-            M *= 2
-            n_p = max(64, N // (F * M))
         snr = rng.uniform(2.0, 8.0, F)
         cfg = dict(n_filters=F, n_pe=M, n_per_pe=n_p, width=side, height=side, patch=9,
                    mode=MODE_ARNA, init_mode=INIT_TRACKING, lik_mode=LIK_PATCH,

@@ -5,7 +5,13 @@
 //                  iterations, one graph replayed) or pf_batch_run_noalloc
 //                  (2); results compared bit for bit
 //   traj           pf_run_traj's rows against pf_estimate after each step
+//   stream         the streaming step kernel (N_p > PF_MAX_PER_PE_LDS) against
+//                  k_step on PEs both can run, every traced output compared
+//                  after each iteration; then contexts of up to 65536
+//                  particles per PE through pf_step, their ancestors checked
+//                  against systematic resampling of the traced weights
 #include "src/arna.hip"
+#include <algorithm>
 #include <random>
 #include <vector>
 
@@ -247,12 +253,169 @@ static int traj_main() {
     return bad ? 2 : 0;
 }
 
+// One iteration of context c by the streaming kernel, whatever its N_p.
+static int launch_stream(pf_ctx *c, const float *frame, float *u) {
+    const uint64_t k = c->step + 1;
+    int rc = ensure_ring(c, k);
+    if (rc != PF_OK) return rc;
+    StepArgs a = make_args(c, k, frame);
+    void *fn = pick_stream_kernel(c->half, c->cfg.lik_mode);
+    void *args[] = {&a, &u};
+    if (hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(kStreamBlock), args, stream_lds_bytes(),
+                        c->stream) != hipSuccess)
+        return PF_EHIP;
+    advance(c, k);
+    return PF_OK;
+}
+
+template <class T>
+static std::vector<T> dbg(pf_ctx *c, int which) {
+    std::vector<T> v(pf_debug_size(c, which) / sizeof(T));
+    check(pf_debug_get(c, which, v.data(), v.size() * sizeof(T)), "debug get");
+    return v;
+}
+
+// Ancestors of one PE by systematic resampling, exact integer arithmetic:
+// rank j goes to min { i : n C_i > j T + V }.
+static std::vector<uint32_t> systematic(const uint32_t *q, uint32_t n, uint32_t V, uint64_t T) {
+    std::vector<uint32_t> anc(n, 0);
+    if (T == 0) return anc;
+    uint64_t C = 0;
+    uint32_t i = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint64_t ptr = (uint64_t)j * T + V;
+        while (i < n && (uint64_t)n * (C + q[i]) <= ptr) C += q[i++];
+        anc[j] = i < n ? i : n - 1;
+    }
+    return anc;
+}
+
+static int stream_main() {
+    int bad = 0;
+    std::mt19937_64 rng(99);
+    // (1) the same iterations by both kernels, from the same state
+    const Case same[] = {
+        {1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 1},
+        {2, 3, 1000, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 2},
+        {1, 3, 4096, 128, 128, 1, 2, 9, 0, 0, 0.1f, 10.f, 2.f, 3},
+        {3, 2, 77, 128, 128, 0, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 4},
+        {1, 4, 3000, 64, 64, 1, 0, 5, 0, 0, 0.1f, 5.f, 2.f, 5},
+        {1, 1, 2000, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 6},
+    };
+    for (const Case &cs : same) {
+        const int K = 5;
+        Inputs in = make_inputs(cs, K, rng);
+        float *d, *u;
+        hipMalloc(&d, in.frames.size() * 4);
+        memcpy(d, in.frames.data(), in.frames.size() * 4);
+        pf_config cfg = make_cfg(cs);
+        cfg.debug = PF_DEBUG_TRACE;
+        pf_ctx *a, *b;
+        check(pf_init(&cfg, in.truth.data(), &a), "init a");
+        check(pf_init(&cfg, in.truth.data(), &b), "init b");
+        hipMalloc(&u, b->N * 4);
+        int diff = 0;
+        double worst = 0;
+        for (int k = 0; k < K; ++k) {
+            check(launch_step(a, d + k * in.stride), "k_step");
+            check(launch_stream(b, d + k * in.stride, u), "k_step_stream");
+            hipDeviceSynchronize();
+            const size_t N = a->N;
+            diff += memcmp(a->prop[a->cur], b->prop[b->cur], 5 * N * 4) != 0;
+            diff += memcmp(a->anc[a->cur], b->anc[b->cur], N * 2) != 0;
+            const int exact[] = {PF_DBG_RING, PF_DBG_NEX, PF_DBG_SRC, PF_DBG_PROP, PF_DBG_ELL,
+                                 PF_DBG_Q, PF_DBG_ANCESTORS, PF_DBG_V};
+            for (int w : exact) {
+                std::vector<unsigned char> x = dbg<unsigned char>(a, w), y = dbg<unsigned char>(b, w);
+                if (x != y) {
+                    fprintf(stderr, "np=%u step %d: debug buffer %d differs\n", cs.np, k, w);
+                    ++diff;
+                }
+            }
+            for (uint64_t i = 0; i < a->FM; ++i) {
+                const pf_pe_record &ra = a->rec[a->cur][i], &rb = b->rec[b->cur][i];
+                diff += ra.lstar != rb.lstar || ra.total_q != rb.total_q;
+                const double dl = fabs(ra.log_mass - rb.log_mass);
+                worst = dl > worst ? dl : worst;
+                diff += !(dl <= 1e-12 * (1 + fabs(ra.log_mass)));
+                for (int c = 0; c < 5; ++c) {
+                    const double dx = fabs(ra.xhat[c] - rb.xhat[c]);
+                    worst = dx > worst ? dx : worst;
+                    diff += !(dx <= 1e-12 * (1 + fabs(ra.xhat[c])));
+                }
+            }
+            // the next iteration starts from the same records
+            memcpy(b->rec[b->cur], a->rec[a->cur], a->FM * sizeof(pf_pe_record));
+        }
+        fprintf(stderr, "np=%u M=%u lik=%u: %s (largest record difference %.3g)\n", cs.np, cs.M,
+                cs.lik, diff ? "DIFFERENT" : "same", worst);
+        bad += diff != 0;
+        pf_destroy(a);
+        pf_destroy(b);
+        hipFree(u);
+        hipFree(d);
+    }
+    // (2) contexts beyond the LDS stage, through the library
+    const Case big[] = {
+        {1, 2, 5000, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},
+        {2, 3, 8192, 96, 96, 0, 2, 9, 1024, 0, 0.5f, 10.f, 2.f, 12},
+        {1, 3, 4097, 64, 64, 1, 1, 9, 0, 0, 0.1f, 5.f, 1.f, 13},
+        {1, 2, 65536, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 14},
+    };
+    for (const Case &cs : big) {
+        const int K = 3;
+        Inputs in = make_inputs(cs, K, rng);
+        float *d;
+        hipMalloc(&d, in.frames.size() * 4);
+        memcpy(d, in.frames.data(), in.frames.size() * 4);
+        pf_config cfg = make_cfg(cs);
+        cfg.debug = PF_DEBUG_TRACE;
+        pf_ctx *c;
+        check(pf_init(&cfg, in.truth.data(), &c), "init big");
+        int diff = 0;
+        size_t distinct = 0;
+        uint32_t nex = 0;
+        for (int k = 0; k < K; ++k) {
+            check(pf_step(c, d + k * in.stride), "step big");
+            nex = dbg<uint32_t>(c, PF_DBG_NEX)[0];
+            std::vector<uint32_t> q = dbg<uint32_t>(c, PF_DBG_Q), anc = dbg<uint32_t>(c, PF_DBG_ANCESTORS),
+                                  v = dbg<uint32_t>(c, PF_DBG_V);
+            std::vector<pf_pe_record> rec = dbg<pf_pe_record>(c, PF_DBG_PE_RECORDS);
+            std::vector<uint16_t> a16(c->N);
+            memcpy(a16.data(), c->anc[c->cur], c->N * 2);
+            for (uint64_t pe = 0; pe < c->FM; ++pe) {
+                const uint32_t *qp = q.data() + pe * cs.np;
+                uint64_t T = 0;
+                for (uint32_t i = 0; i < cs.np; ++i) T += qp[i];
+                diff += T != rec[pe].total_q;
+                const std::vector<uint32_t> want = systematic(qp, cs.np, v[pe], T);
+                for (uint32_t j = 0; j < cs.np; ++j)
+                    diff += want[j] != anc[pe * cs.np + j] || want[j] != a16[pe * cs.np + j];
+                if (pe == 0) {
+                    std::vector<uint32_t> w = want;
+                    std::sort(w.begin(), w.end());
+                    distinct = std::unique(w.begin(), w.end()) - w.begin();
+                }
+            }
+        }
+        fprintf(stderr, "np=%u M=%u lik=%u through pf_step: %s (last iteration: N_ex %u, "
+                "%zu distinct ancestors in PE 0)\n", cs.np, cs.M, cs.lik,
+                diff ? "WRONG ANCESTORS" : "ancestors exact", nex, distinct);
+        bad += diff != 0;
+        pf_destroy(c);
+        hipFree(d);
+    }
+    fprintf(stderr, bad ? "STREAM MISMATCH\n" : "STREAM EQUAL\n");
+    return bad ? 2 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc > 1 && !strcmp(argv[1], "batch")) {
         if (argc > 4) emu_set_fill(atoi(argv[4]));
         return batch_main(argc > 2 ? atoi(argv[2]) : 70, argc > 3 ? atoi(argv[3]) : 0);
     }
     if (argc > 1 && !strcmp(argv[1], "traj")) return traj_main();
-    fprintf(stderr, "usage: %s batch K MODE [FILL] | traj\n", argv[0]);
+    if (argc > 1 && !strcmp(argv[1], "stream")) return stream_main();
+    fprintf(stderr, "usage: %s batch K MODE [FILL] | traj | stream\n", argv[0]);
     return 1;
 }

@@ -75,7 +75,7 @@ def test_strerror_texts(L):
 
 
 def _init(L, **kw):
-    c = make_config(kw)
+    c = make_config(kw, debug=kw.get("debug", 0))
     for k, v in kw.items():
         if k == "struct_size":
             c.struct_size = v
@@ -108,6 +108,12 @@ def _init(L, **kw):
     (dict(block_size=100), nat.PF_EINVAL),             # not a multiple of 64
     (dict(block_size=2048), nat.PF_EINVAL),            # above 1024
     (dict(n_per_pe=4096, block_size=512), nat.PF_EINVAL),   # 4 slots per thread do not cover N_p
+    # PEs beyond the LDS stage: the streaming kernel's 1024 threads only, and
+    # none of lineage tags, multi-iteration launches, 2048 or more PEs
+    (dict(n_per_pe=5000, block_size=512), nat.PF_EINVAL),
+    (dict(n_per_pe=5000, debug=nat.PF_DEBUG_LINEAGE), nat.PF_EUNSUPPORTED),
+    (dict(n_per_pe=5000, launch=nat.PF_LAUNCH_PERSISTENT), nat.PF_EUNSUPPORTED),
+    (dict(n_per_pe=8192, n_pe=2048), nat.PF_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_config_on_host(L, bad, code):
     assert _init(L, **bad) == code
@@ -162,8 +168,8 @@ def test_limit_constants_match_header():
     """The binding's size limits are the header's #defines."""
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     defs = dict(re.findall(r"#define\s+(PF_\w*MAX_\w+)\s+(.+)", text))
-    assert set(defs) == {"PF_MAX_PE", "PF_MAX_PER_PE", "PF_MAX_PATCH", "PF_MAX_PARTICLES",
-                         "PF_BATCH_NOALLOC_MAX_ARGS"}
+    assert set(defs) == {"PF_MAX_PE", "PF_MAX_PER_PE", "PF_MAX_PER_PE_LDS", "PF_MAX_PATCH",
+                         "PF_MAX_PARTICLES", "PF_BATCH_NOALLOC_MAX_ARGS"}
     for name, expr in defs.items():
         val = eval(re.sub(r"(\d+)u\b", r"\1", expr.strip()), {})
         assert getattr(nat, name) == val, name

@@ -75,7 +75,7 @@ def test_device_exchange_count_bit_exact():
     rng = np.random.Generator(np.random.PCG64(2))
     for trial in range(200):
         M = int(rng.integers(1, 8193 if trial % 20 == 0 else 400))
-        n_p = int(rng.integers(1, 4097))
+        n_p = int(rng.integers(1, 65537 if trial % 4 == 0 else 4097))
         P = np.floor(np.exp(-rng.exponential(rng.uniform(0.05, 8), M)) * 2 ** 20).astype(np.uint32)
         P[rng.integers(0, M)] = 1 << 20
         for mode, first in [(1, False), (1, True), (0, False)]:
@@ -181,6 +181,38 @@ def seeded_case(name):
         state = synth.random_state(rng, F, M, n_p, cfg["width"], cfg["height"], spread=spread,
                                    centre=centre, I0=10.0)
         return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (F, M))
+    elif name in ("arna_2x4x16384", "arna_1x3x65536"):
+        # PEs beyond the LDS stage (the streaming step): 2 spots on 256^2
+        # around which the particles sit, and 1 spot on 512^2 with the
+        # particles spread wider (patches from the tile and from the frame)
+        F, M, n_p, side, spread = ((2, 4, 16384, 256, 1.5) if name == "arna_2x4x16384"
+                                   else (1, 3, 65536, 512, 6.0))
+        cfg = dict(n_filters=F, n_pe=M, n_per_pe=n_p, width=side, height=side, patch=9,
+                   mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 8 + F)
+        truth = np.array([[[0.3 * side + 0.4, 0.6 * side + 0.7, 0, 0, 12.0],
+                           [0.7 * side + 0.1, 0.3 * side + 0.2, 0, 0, 9.0]][:F]])
+        frame = synth.render(truth[0], side, side, 1.5, 5.0, 2.0, rng)
+        state = synth.random_state(rng, F, M, n_p, side, side, spread=spread,
+                                   centre=truth[0, :, :2], I0=10.0)
+        return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (F, M))
+    elif name == "poisson_rna_1x2x20000":
+        # ragged streaming PEs (20000 = 312 x 64 + 32) exchanging half their slots
+        cfg = dict(n_filters=1, n_pe=2, n_per_pe=20000, width=128, height=96, patch=9,
+                   mode=0, init_mode=0, lik_mode=2, fixed_ratio=0.5, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=10.0, noise_sigma=1.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 11)
+        truth = np.array([[[40.4, 50.6, 0, 0, 20.0]]])
+        frame = synth.render_poisson(truth[0], 128, 96, 1.5, 10.0, rng)
+        centre = truth[0, :, :2]
+    elif name == "point_arna_2x3x5000":
+        cfg = dict(n_filters=2, n_pe=3, n_per_pe=5000, width=128, height=128, patch=9,
+                   mode=1, init_mode=0, lik_mode=1, fixed_ratio=0.1, initial_ratio=0.1,
+                   eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=1.0, q=0.5,
+                   sigma_I=0.5, seed=SEED + 12)
+        centre = rng.uniform(20, 100, (2, 2))
+        frame = (centre + rng.standard_normal((2, 2))).astype(np.float32)
     elif name == "point_rna_3x5x77":
         cfg = dict(n_filters=3, n_pe=5, n_per_pe=77, width=128, height=128, patch=9,
                    mode=0, init_mode=0, lik_mode=1, fixed_ratio=0.5, initial_ratio=0.1,
@@ -231,6 +263,14 @@ def test_one_step_parity(name, k_done):
     check_one_step(name, k_done)
 
 
+@pytest.mark.parametrize("name", ["arna_2x4x16384", "arna_1x3x65536", "poisson_rna_1x2x20000",
+                                  "point_arna_2x3x5000"])
+@pytest.mark.parametrize("k_done", [0, 7])
+def test_one_step_parity_streaming(name, k_done):
+    """PEs of more than 4096 particles (the streaming step kernel), every PE."""
+    check_one_step(name, k_done)
+
+
 def test_one_step_parity_2e24():
     """The tracking workload at 2^24 particles (64 filters x 64 PEs x 4096,
     4096 workgroups), one step after seven."""
@@ -245,7 +285,7 @@ def check_one_step(name, k_done):
 
 
 BATCH_CASES = ["rna_128_4x256", "arna_ragged_2x3x100", "arna_1x6x2500", "poisson_arna_1x4x1000",
-               "point_rna_3x5x77", "arna_groups_2x24x300"]
+               "point_rna_3x5x77", "arna_groups_2x24x300", "point_arna_2x3x5000"]
 
 
 def test_one_step_parity_batched():
@@ -343,8 +383,42 @@ def compare_one_step(cfg, frame, g, tr, k_done):
           f"log_z err {np.abs(g['est']['log_z_inc'] - ref['log_z']).max():.3g}", flush=True)
     assert np.all(err_l <= lim_l), float((err_l - lim_l).max())
     assert np.allclose(g["est"]["log_z_inc"], ref["log_z"], rtol=1e-5, atol=1e-3)
-    assert np.array_equal(g["est"]["n_ex_next"], ref["n_ex_next"])
     assert np.allclose(g["est"]["pe_eff"], ref["pe_eff"], rtol=1e-4)
+    check_next_nex(cfg, rec[:, :, 0], g["est"]["n_ex_next"], ref["n_ex_next"], lim_l)
+
+
+def check_next_nex(cfg, L_gpu, nex_gpu, nex_orc, lim_l):
+    """N_ex of the next iteration is an integer decided by floating point (the
+    PE log-masses, through P_m = floor(exp(L_m - max L) 2^20)).  The device's
+    value must be the exact rule (Eq. 3 and 4 in integers, the oracle's
+    routine) applied to the device's own records.  The oracle's value comes
+    from its own L_m, which differ within lim_l: a change of every L_m by at
+    most d moves S^2 / D = PE_eff by a factor within exp(+-4 d), hence N_ex =
+    N_p / 2 (1 - (PE_eff - 1) / (M - 1)) by at most N_p PE_eff (e^{4d} - 1) /
+    (2 (M - 1)) + 1; across the cut-off (PE_eff > c M: no exchange) either
+    side may be taken."""
+    F, M, n_p = cfg["n_filters"], cfg["n_pe"], cfg["n_per_pe"]
+    for f in range(F):
+        L = L_gpu[f]
+        if not np.isfinite(L.max()):
+            continue
+        P = np.floor(np.exp(L - L.max()) * 2.0 ** 20)
+        want = orc.nex(P.astype(np.uint32), n_p, mode=cfg["mode"],
+                       fixed_ratio=cfg["fixed_ratio"], initial_ratio=cfg["initial_ratio"],
+                       cutoff=cfg["eff_cutoff"], first=False)
+        assert int(nex_gpu[f]) == want, (f, int(nex_gpu[f]), want)
+        if int(nex_gpu[f]) == int(nex_orc[f]):
+            continue
+        assert cfg["mode"] == 1 and M > 1, (f, int(nex_gpu[f]), int(nex_orc[f]))
+        d = float(np.max(lim_l[f]))
+        S = P.sum()
+        eff = S * S / float((P * P).sum())
+        grow = np.expm1(4 * d)
+        bound = n_p * eff * grow / (2 * (M - 1)) + 1
+        near_cut = abs(eff - cfg["eff_cutoff"] * M) <= eff * grow
+        ok = abs(int(nex_gpu[f]) - int(nex_orc[f])) <= bound or (
+            near_cut and 0 in (int(nex_gpu[f]), int(nex_orc[f])))
+        assert ok, (f, int(nex_gpu[f]), int(nex_orc[f]), bound)
 
 
 def test_master_step_of_many_pes():
@@ -389,6 +463,22 @@ def test_exchange_map_export():
     tr = o.step(frame, want={"src_map"})
     assert np.array_equal(src.cpu().numpy(), tr["src_map"])
     g.step(torch.from_numpy(frame).cuda())   # steps 4-10 after the exported exchange
+    g.close()
+
+
+def test_exchange_map_export_streaming():
+    """The source map of a context beyond the LDS stage (computed slot by
+    slot) against the oracle's."""
+    p = pf()
+    cfg, frame, state, logmass = seeded_case("poisson_rna_1x2x20000")
+    g = p.Tracker(cfg, np.zeros((1, 5), np.float32))
+    g.set_state(state, logmass, step=2)
+    src = torch.zeros(g.N, dtype=torch.int64, device="cuda")
+    g.exchange(src)
+    o = orc.Oracle(cfg, np.zeros((1, 5), np.float32))
+    o.set_state(state.astype(np.float64), logmass, 2)
+    tr = o.step(frame, want={"src_map"})
+    assert np.array_equal(src.cpu().numpy(), tr["src_map"])
     g.close()
 
 

@@ -75,3 +75,11 @@ def test_batched_run_with_zeroed_fresh_memory(checks):
 def test_trajectory_rows_equal_stepwise_estimates(checks):
     rc, err = _run(checks, "traj")
     assert rc == 0 and "TRAJ EQUAL" in err, err[-4000:]
+
+
+def test_streaming_kernel_equals_lds_kernel_and_resamples_exactly(checks):
+    # PEs of up to 4096 particles: every traced output of the streaming step
+    # equals k_step's; 4097..65536 particles per PE: ancestors equal exact
+    # systematic resampling of the traced weights
+    rc, err = _run(checks, "stream")
+    assert rc == 0 and "STREAM EQUAL" in err, err[-4000:]
