@@ -65,10 +65,10 @@ enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the
 /* Up to this many particles per PE a PE's particles live in LDS for the whole
  * iteration.  Larger PEs stream them through HBM (a second step kernel with the
  * same results up to the summation order of the FP64 PE sums): such contexts
- * take no block_size other than 0 or 1024, no PF_DEBUG_LINEAGE, no
- * PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no gradient recording
- * (PF_EUNSUPPORTED), run in a batch one by one, and hold N more floats of
- * device memory (the log-weights of the iteration). */
+ * take no block_size other than 0 or 1024, no pes_per_wg above 1 (PF_EINVAL),
+ * no PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no
+ * gradient recording (PF_EUNSUPPORTED), run in a batch one by one, and hold N
+ * more floats of device memory (the log-weights of the iteration). */
 #define PF_MAX_PER_PE_LDS 4096u
 #define PF_MAX_PATCH 15u
 #define PF_MAX_PARTICLES (1u << 29)   /* F M N_p: state indices are 32-bit (5 F M N_p < 2^32) */
@@ -129,6 +129,18 @@ typedef struct {
                                  * cooperative launch it needs costs about 1 ms once the
                                  * process uses three or more other streams, so AUTO does
                                  * not choose it. */
+    uint32_t pes_per_wg;        /* PEs per workgroup: 0 or 1 = one (k_step); P in 2..16 = P
+                                 * PEs of one filter share a workgroup, each on its own
+                                 * group of whole waves (block_size / P threads, a multiple
+                                 * of 64, with block_size / P * 4 >= N_p; block_size 0 = P
+                                 * times N_p rounded up to 64, at most 1024 / P): the PEs
+                                 * share the image tile, the barriers and the launch's
+                                 * workgroup count, which pays for small N_p.  Same
+                                 * results as one PE per workgroup up to the summation
+                                 * order of the FP64 PE sums.  N_p <= PF_MAX_PER_PE_LDS;
+                                 * no PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, no
+                                 * gradient recording (PF_EUNSUPPORTED); a batch runs such
+                                 * contexts one by one.  The autotuner's second axis. */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;

@@ -48,6 +48,7 @@ class pf_config(ctypes.Structure):
         ("ring_groups", ctypes.c_uint32),
         ("block_size", ctypes.c_uint32),
         ("launch", ctypes.c_uint32),
+        ("pes_per_wg", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]

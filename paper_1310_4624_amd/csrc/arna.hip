@@ -67,9 +67,12 @@ struct pf_ctx {
     uint64_t N, FM;
     uint32_t block, ppt, half;
     size_t lds;
-    // N_p > PF_MAX_PER_PE_LDS: the streaming step kernel and its log-weights
-    bool streamk;
-    float *u;                      // [N]
+    // k_step_flex instead of k_step: several PEs per workgroup (ppw > 1), or
+    // N_p > PF_MAX_PER_PE_LDS (streamk: log-weights in u [N], one PE per
+    // workgroup); n_wg workgroups per launch
+    bool flex, streamk;
+    uint32_t ppw, n_wg;
+    float *u;
     float *prop[2];
     uint16_t *anc[2];
     pf_pe_record *rec[2];
@@ -238,36 +241,52 @@ void *pick_step_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
     return pick_patch_kernel<kLikGauss>(ppt, half);
 }
 
-template <int HALF, int LIK>
-void *stream_kernel() {
-    return reinterpret_cast<void *>(&k_step_stream<HALF, LIK>);
+template <int HALF, int LIK, bool ULDS>
+void *flex_kernel() {
+    return reinterpret_cast<void *>(&k_step_flex<HALF, LIK, ULDS>);
 }
 
-template <int LIK>
-void *pick_stream_patch_kernel(uint32_t half) {
+template <int LIK, bool ULDS>
+void *pick_flex_patch_kernel(uint32_t half) {
     switch (half) {
-        case 0: return stream_kernel<0, LIK>();
-        case 1: return stream_kernel<1, LIK>();
-        case 2: return stream_kernel<2, LIK>();
-        case 3: return stream_kernel<3, LIK>();
-        case 4: return stream_kernel<4, LIK>();
-        case 5: return stream_kernel<5, LIK>();
-        case 6: return stream_kernel<6, LIK>();
-        case 7: return stream_kernel<7, LIK>();
+        case 0: return flex_kernel<0, LIK, ULDS>();
+        case 1: return flex_kernel<1, LIK, ULDS>();
+        case 2: return flex_kernel<2, LIK, ULDS>();
+        case 3: return flex_kernel<3, LIK, ULDS>();
+        case 4: return flex_kernel<4, LIK, ULDS>();
+        case 5: return flex_kernel<5, LIK, ULDS>();
+        case 6: return flex_kernel<6, LIK, ULDS>();
+        case 7: return flex_kernel<7, LIK, ULDS>();
         default: return nullptr;
     }
 }
 
-void *pick_stream_kernel(uint32_t half, uint32_t lik_mode) {
-    if (lik_mode == PF_LIK_POINT) return stream_kernel<0, kLikPoint>();
-    if (lik_mode == PF_LIK_POISSON) return pick_stream_patch_kernel<kLikPoisson>(half);
-    return pick_stream_patch_kernel<kLikGauss>(half);
+template <bool ULDS>
+void *pick_flex_kernel_u(uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT) return flex_kernel<0, kLikPoint, ULDS>();
+    if (lik_mode == PF_LIK_POISSON) return pick_flex_patch_kernel<kLikPoisson, ULDS>(half);
+    return pick_flex_patch_kernel<kLikGauss, ULDS>(half);
+}
+
+// ulds: log-weights in LDS (several PEs per workgroup), else in HBM (PEs
+// beyond the LDS stage)
+void *pick_flex_kernel(uint32_t half, uint32_t lik_mode, bool ulds) {
+    return ulds ? pick_flex_kernel_u<true>(half, lik_mode)
+                : pick_flex_kernel_u<false>(half, lik_mode);
 }
 
 // The one-iteration kernel of a context.
 void *ctx_step_kernel(const pf_ctx *c) {
-    return c->streamk ? pick_stream_kernel(c->half, c->cfg.lik_mode)
-                      : pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
+    return c->flex ? pick_flex_kernel(c->half, c->cfg.lik_mode, !c->streamk)
+                   : pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
+}
+
+// Threads per PE of a context with several PEs per workgroup: N_p rounded up
+// to 64, at most 1024 / ppw (rounded down to 64).
+uint32_t group_threads(uint32_t np, uint32_t ppw) {
+    const uint32_t cap = 1024 / ppw / 64 * 64;
+    const uint32_t want = (np + 63) / 64 * 64;
+    return want < cap ? want : cap;
 }
 
 // Batched variants exist for the paper's 9 x 9 patch (Gaussian or Poisson
@@ -331,13 +350,25 @@ int validate(const pf_config *c) {
     if (c->mode > 1 || c->init_mode > 1 || c->lik_mode > 2) return PF_EINVAL;
     if (c->ring_groups > 256) return PF_EINVAL;
     if (c->launch > PF_LAUNCH_PERSISTENT) return PF_EINVAL;
-    if (c->n_per_pe > PF_MAX_PER_PE_LDS) {
-        // the streaming kernel: 1024 threads, no lineage tags, no multi-iteration
-        // launch, no once-per-filter master record
-        if (c->block_size && c->block_size != kStreamBlock) return PF_EINVAL;
-        if ((c->debug & PF_DEBUG_LINEAGE) || c->launch == PF_LAUNCH_PERSISTENT ||
-            c->n_pe >= kMasterMinPE)
+    if (c->pes_per_wg > kMaxPesPerWg) return PF_EINVAL;
+    if (c->pes_per_wg > 1 || c->n_per_pe > PF_MAX_PER_PE_LDS) {
+        // k_step_flex: no lineage tags, no multi-iteration launch
+        if ((c->debug & PF_DEBUG_LINEAGE) || c->launch == PF_LAUNCH_PERSISTENT)
             return PF_EUNSUPPORTED;
+    }
+    if (c->n_per_pe > PF_MAX_PER_PE_LDS) {
+        // one streamed PE per workgroup of 1024 threads, without the
+        // once-per-filter master record
+        if (c->pes_per_wg > 1) return PF_EINVAL;
+        if (c->block_size && c->block_size != kStreamBlock) return PF_EINVAL;
+        if (c->n_pe >= kMasterMinPE) return PF_EUNSUPPORTED;
+    } else if (c->pes_per_wg > 1) {
+        // ppw groups of whole waves, at most 4 slots per thread
+        const uint32_t ppw = c->pes_per_wg;
+        const uint32_t B = c->block_size ? c->block_size
+                                         : ppw * group_threads(c->n_per_pe, ppw);
+        if (B == 0 || B > 1024 || B % (64 * ppw)) return PF_EINVAL;
+        if ((uint64_t)(B / ppw) * 4 < c->n_per_pe) return PF_EINVAL;
     } else if (c->block_size) {
         if (c->block_size % 64 || c->block_size > 1024) return PF_EINVAL;
         if ((uint64_t)c->block_size * 4 < c->n_per_pe) return PF_EINVAL;
@@ -487,8 +518,8 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
     StepArgs a = make_args(c, k, frame, traj_prev);
     void *fn = ctx_step_kernel(c);
     if (!fn) return PF_EUNSUPPORTED;
-    void *args[] = {&a, &c->u};   // (the LDS kernel takes the first only)
-    HIP_OK(hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(c->block), args, c->lds, c->stream));
+    void *args[] = {&a, &c->u, &c->ppw};   // (k_step takes the first only)
+    HIP_OK(hipLaunchKernel(fn, dim3(c->n_wg), dim3(c->block), args, c->lds, c->stream));
     advance(c, k);
     return PF_OK;
 }
@@ -683,8 +714,14 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->FM = (uint64_t)F * M;
     c->N = c->FM * np;
     c->streamk = np > PF_MAX_PER_PE_LDS;
+    c->ppw = cfg->pes_per_wg > 1 ? cfg->pes_per_wg : 1;
+    c->flex = c->streamk || c->ppw > 1;
+    c->n_wg = (uint32_t)((uint64_t)F * ((M + c->ppw - 1) / c->ppw));
     if (c->streamk) {
         c->block = kStreamBlock;
+        c->ppt = 0;
+    } else if (c->ppw > 1) {
+        c->block = cfg->block_size ? cfg->block_size : c->ppw * group_threads(np, c->ppw);
         c->ppt = 0;
     } else if (cfg->block_size) {
         c->block = cfg->block_size;
@@ -696,7 +733,8 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->half = cfg->lik_mode != PF_LIK_POINT ? cfg->patch / 2 : 0;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
-    c->lds = c->streamk ? stream_lds_bytes() : step_lds(np, lineage);
+    c->lds = c->streamk ? flex_lds_bytes(0)
+                        : (c->flex ? flex_lds_bytes(c->ppw * np) : step_lds(np, lineage));
     c->key0 = (uint32_t)cfg->seed;
     c->key1 = (uint32_t)(cfg->seed >> 32);
     c->fixed_nex = fixed_count(cfg->fixed_ratio, np);
@@ -936,7 +974,7 @@ void pf_destroy(pf_ctx *c) {
 
 int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
     if (!c || max_steps == 0) return PF_EINVAL;
-    if (c->cfg.lik_mode != PF_LIK_PATCH || c->streamk) return PF_EUNSUPPORTED;
+    if (c->cfg.lik_mode != PF_LIK_PATCH || c->flex) return PF_EUNSUPPORTED;
     if (!(c->cfg.q > 0.f)) return PF_EINVAL;
     if (c->g_cap || c->exchanged) return PF_ESTATE;
     const uint64_t N = c->N, FM = c->FM;
@@ -1108,7 +1146,7 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
     b->args_cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
         pf_ctx *c = ctxs[i];
-        void *fn = c->streamk ? nullptr : pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
+        void *fn = c->flex ? nullptr : pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
         if (!fn || c->FM > 0xFFFFFFFFull) {
             b->solo.push_back(i);
             continue;

@@ -1,16 +1,23 @@
-// The ARNA / RNA iteration for PEs whose particles do not fit the LDS stage of
-// k_step (PF_MAX_PER_PE_LDS < N_p <= PF_MAX_PER_PE): one workgroup of 1024
-// threads per PE, as in k_step, with the particles streamed through HBM.  The
-// data layout is k_step's (propagated particles plus a 16-bit ancestor slot),
-// so the two kernels compute the same iteration on the same buffers.
-//
-//   pass A (slots t + i B): the slot's particle -- its own through its
+// The ARNA / RNA iteration with a flexible mapping of PEs to workgroups, for
+// the PE sizes at either end of k_step's range:
+//   * several PEs per workgroup (P = 2..16 PEs of one filter, each on its own
+//     group of whole waves): small PEs share one image tile and one set of
+//     barriers, and their log-weights live in LDS;
+//   * one PE whose particles do not fit the LDS stage of k_step
+//     (PF_MAX_PER_PE_LDS < N_p <= PF_MAX_PER_PE): the log-weights go to a
+//     per-context HBM array.
+// The data layout is k_step's (propagated particles plus a 16-bit ancestor
+// slot), so the kernels compute the same iteration on the same buffers: Q,
+// ancestors and every traced value are k_step's bit for bit, and only the
+// FP64 PE sums are added in another order.  Per PE, on its thread group of
+// tp threads:
+//   pass A (slots t + i tp): the slot's particle -- its own through its
 //     ancestor, or pred's slot s_t(pred) (Alg. 3 step 3) -- the step-5
 //     normals and propagation, the patch likelihood (LDS tile or frame, as in
-//     k_step) and u = lambda + l, stored in the context's log-weight array;
-//   pass B (wave w takes the contiguous slots [w C, (w + 1) C), 64 at a time):
-//     Q = floor(w Q_max) with w = exp(u - max u), the per-PE FP64 sums of
-//     step 6, the wave's total of Q;
+//     k_step) and u = lambda + l;
+//   pass B (the PE's wave w takes the contiguous slots [w C, (w + 1) C), 64
+//     at a time): Q = floor(w Q_max) with w = exp(u - max u), the per-PE FP64
+//     sums of step 6, the wave's total of Q;
 //   pass C (the same slots): inclusive sums C_i of Q in slot order (one wave
 //     scan per 64 slots plus the carry of the earlier ones).  The particles of
 //     64 consecutive slots own the consecutive output ranks
@@ -20,30 +27,34 @@
 //     the lanes' first ranks.  These are the ancestors k_step finds from its
 //     offspring marks (rank j goes to min { i : N_p C_i > j T + V }), with
 //     O(N_p) work however degenerate the weights are;
-//   then the PE record (steps 8-9).
-// Contexts of this size use neither lineage tags nor the once-per-filter
-// master record (M >= 2048), and are never batched.
+//   then thread 0 writes the workgroup's PE records (steps 8-9) and, with the
+//   once-per-filter master record (M >= 2048), the last workgroup of the
+//   filter computes it.
 #pragma once
 
 #include "arna_kernels.hpp"
 
 namespace {
 
-constexpr uint32_t kStreamBlock = 1024;
+constexpr uint32_t kStreamBlock = 1024;   // threads of a streamed PE's workgroup
+constexpr uint32_t kMaxPesPerWg = 16;
 
-struct StreamLds {
+struct FlexLds {
     float *tile;       // [kTileRows][kTilePitch]
     double *wsum;      // [16][6] wave sums (W, W x)
     float *wmax;       // [16] wave maxima of u
     uint32_t *wq;      // [16] wave totals of Q
-    Prologue *pro;     // 1
+    uint32_t *flag;    // 1 (+3 padding)
+    Prologue *pro;     // [kMaxPesPerWg]
+    float *u;          // [P N_p] log-weights (when they stay in LDS)
 };
-__host__ __device__ constexpr size_t stream_lds_bytes() {
+__host__ __device__ constexpr size_t flex_lds_bytes(uint32_t u_slots) {
     return (size_t)kTileRows * kTilePitch * sizeof(float) + kMaxWaves * 6 * sizeof(double) +
-           kMaxWaves * sizeof(float) + kMaxWaves * sizeof(uint32_t) + 32;
+           kMaxWaves * sizeof(float) + kMaxWaves * sizeof(uint32_t) + 16 +
+           kMaxPesPerWg * sizeof(Prologue) + (size_t)u_slots * sizeof(float);
 }
-__device__ __forceinline__ StreamLds stream_carve(unsigned char *base) {
-    StreamLds l;
+__device__ __forceinline__ FlexLds flex_carve(unsigned char *base) {
+    FlexLds l;
     size_t o = 0;
     l.tile = (float *)(base + o);
     o += (size_t)kTileRows * kTilePitch * sizeof(float);
@@ -53,7 +64,11 @@ __device__ __forceinline__ StreamLds stream_carve(unsigned char *base) {
     o += kMaxWaves * sizeof(float);
     l.wq = (uint32_t *)(base + o);
     o += kMaxWaves * sizeof(uint32_t);
+    l.flag = (uint32_t *)(base + o);
+    o += 16;
     l.pro = (Prologue *)(base + o);
+    o += kMaxPesPerWg * sizeof(Prologue);
+    l.u = (float *)(base + o);
     return l;
 }
 
@@ -65,34 +80,52 @@ __device__ __forceinline__ uint32_t stream_q(float u, float lstar, float qmaxf, 
     return (uint32_t)qf;
 }
 
-// u: [N] log-weights of the iteration (context scratch, fully rewritten).
-template <int HALF, int LIK>
-__global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
+// A value the same in every lane of the wave, kept in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uni(float v) { return __uint_as_float(uni(__float_as_uint(v))); }
+
+// ppw PEs of one filter per workgroup (tp = blockDim.x / ppw threads each, a
+// multiple of 64; workgroup g of filter f holds PEs g ppw .. g ppw + ppw - 1,
+// the last workgroup of a filter possibly fewer).  ULDS: the log-weights stay
+// in LDS (ppw N_p floats); else they go to u_hbm [N] (context scratch, fully
+// rewritten).
+template <int HALF, int LIK, bool ULDS>
+__global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int P = 2 * HALF + 1;
     constexpr bool POINT = LIK == kLikPoint;
-    const uint32_t tid = threadIdx.x, bid = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
     const uint32_t M = a.M, np = a.np, N = a.N;
-    const uint32_t f = bid / M, m = bid % M;
-    const uint32_t B = blockDim.x;
-    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, nwaves = B / kWave;
-    StreamLds L = stream_carve(smem);
-    const uint32_t pe_base = bid * np;
+    const uint32_t B = blockDim.x, tp = B / ppw;
+    const uint32_t G = (M + ppw - 1) / ppw;   // workgroups per filter
+    const uint32_t f = blockIdx.x / G, m0 = (blockIdx.x % G) * ppw;
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
+    // this thread's PE in the group (whole waves per PE: the same in every
+    // lane), its rank in the PE's thread group
+    const uint32_t lp = uni(tid / tp), lt = tid - lp * tp;
+    const uint32_t wpp = tp / kWave, w_first = lp * wpp;   // the PE's waves
+    const uint32_t m = m0 + lp;
+    const bool active = m < M;   // the same in every lane of a wave
+    const uint32_t pe_base = (f * M + m) * np;
+    FlexLds L = flex_carve(smem);
+    float *ub = ULDS ? L.u + lp * np : u_hbm + pe_base;
     const DebugBufs *D = a.dbg;
     const bool trace = D && D->t_q;
 
-    // ---- steps 1-2 (wave 0); the image tile around this PE's estimate of
-    // k-1 moved one step (every thread)
-    if (wave == 0) {
+    // ---- steps 1-2 (the first wave of each PE); the image tile around the
+    // estimate of k-1 of the group's first PE, moved one step (every thread)
+    if (active && lt < kWave) {
         if (a.min)
-            prologue_master(a, f, m, L.pro, tid);
+            prologue_master(a, f, m, L.pro + lp, lane);
         else
-            prologue_wave(a, f, m, L.pro, tid);
+            prologue_wave(a, f, m, L.pro + lp, lane);
     }
     int tx0 = 0, ty0 = 0;
     bool tile_on = false, tile_inside = false;
     if (!POINT) {
-        const double *xh = a.rin[bid].xhat;
+        const double *xh = a.rin[f * M + m0].xhat;
         const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
         if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
             tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
@@ -111,77 +144,90 @@ __global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
                     in ? a.lik.img[(size_t)vv * a.lik.W + uu] - a.lik.bg : 0.f;
             }
     }
-    __syncthreads();   // prologue and tile visible
-    const Prologue p = *L.pro;
-    const uint32_t pred_base = (f * M + p.pred) * np;
+    __syncthreads();   // prologues and tile visible
 
     // ---- pass A (steps 3-5)
     float umax = -INFINITY;
-    bool bad = false;
-    for (uint32_t s = tid; s < np; s += B) {
-        const uint32_t r = received_from(s, p, np);
-        const uint32_t blk = (r == kNoSlot) ? pe_base : pred_base;   // PE whose slot it takes
-        const uint32_t sb = blk + ((r == kNoSlot) ? s : r);          // that resampled slot
-        const float lam = (r == kNoSlot) ? p.lam_own : p.lam_pred;
-        const uint32_t gsrc = blk + a.ain[sb];                         // its propagated particle
-        float x[5], e[5];
+    if (active) {
+        Prologue p = L.pro[lp];
+        p.pred = uni(p.pred);
+        p.nex = uni(p.nex);
+        p.c_own = uni(p.c_own);
+        p.c_pred = uni(p.c_pred);
+        p.lam_own = uni(p.lam_own);
+        p.lam_pred = uni(p.lam_pred);
+        const uint32_t pred_base = (f * M + p.pred) * np;
+        bool bad = false;
+#pragma unroll 1
+        for (uint32_t s = lt; s < np; s += tp) {
+            const uint32_t r = received_from(s, p, np);
+            const uint32_t blk = (r == kNoSlot) ? pe_base : pred_base;   // PE whose slot it takes
+            const uint32_t sb = blk + ((r == kNoSlot) ? s : r);          // that resampled slot
+            const float lam = (r == kNoSlot) ? p.lam_own : p.lam_pred;
+            const uint32_t gsrc = blk + a.ain[sb];                         // its propagated particle
+            float x[5], e[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) x[c] = a.pin[(size_t)c * N + gsrc];
-        five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e);
-        propagate(x, e, a.dyn);
+            for (int c = 0; c < 5; ++c) x[c] = a.pin[(size_t)c * N + gsrc];
+            five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e);
+            propagate(x, e, a.dyn);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) a.pout[(size_t)c * N + pe_base + s] = x[c];
-        float ell = 0.f;
-        int u0, v0;
-        if (POINT) {
-            ell = loglik_point(x, a.lik, f);
-        } else if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
-            const int du = u0 - tx0, dv = v0 - ty0;
-            if (tile_on && (unsigned)du <= (unsigned)(kTileCols - P) &&
-                (unsigned)dv <= (unsigned)(kTileRows - P)) {
-                const float *pix = L.tile + dv * kTilePitch + du;
-                if (LIK == kLikPoisson)
-                    ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, kTilePitch, a.lik);
-                else
-                    ell = tile_inside ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix,
-                                                                            kTilePitch, a.lik)
-                                      : patch_loglik<HALF, kFromTile>(x, u0, v0, pix, kTilePitch,
-                                                                      a.lik);
-            } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W && v0 + P <= (int)a.lik.H) {
-                const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
-                ell = (LIK == kLikPoisson)
-                          ? patch_loglik_poisson<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik)
-                          : patch_loglik<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik);
-            } else {
-                ell = (LIK == kLikPoisson)
-                          ? patch_loglik_poisson<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0,
-                                                                          a.lik)
-                          : patch_loglik<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0, a.lik);
+            for (int c = 0; c < 5; ++c) a.pout[(size_t)c * N + pe_base + s] = x[c];
+            if (trace) {
+                D->t_src[pe_base + s] = (int64_t)sb;
+                D->t_lam[pe_base + s] = lam;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) D->t_prop[(size_t)c * N + pe_base + s] = x[c];
             }
+            float ell = 0.f;
+            int u0, v0;
+            if (POINT) {
+                ell = loglik_point(x, a.lik, f);
+            } else if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
+                const int du = u0 - tx0, dv = v0 - ty0;
+                if (tile_on && (unsigned)du <= (unsigned)(kTileCols - P) &&
+                    (unsigned)dv <= (unsigned)(kTileRows - P)) {
+                    const float *pix = L.tile + dv * kTilePitch + du;
+                    if (LIK == kLikPoisson)
+                        ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, kTilePitch,
+                                                                     a.lik);
+                    else
+                        ell = tile_inside ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix,
+                                                                                kTilePitch, a.lik)
+                                          : patch_loglik<HALF, kFromTile>(x, u0, v0, pix,
+                                                                          kTilePitch, a.lik);
+                } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W &&
+                           v0 + P <= (int)a.lik.H) {
+                    const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
+                    ell = (LIK == kLikPoisson)
+                              ? patch_loglik_poisson<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik)
+                              : patch_loglik<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik);
+                } else {
+                    ell = (LIK == kLikPoisson)
+                              ? patch_loglik_poisson<HALF, kFromImageBorder>(x, u0, v0, a.lik.img,
+                                                                              0, a.lik)
+                              : patch_loglik<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0,
+                                                                     a.lik);
+                }
+            }
+            bad |= (ell != ell);
+            const float us = lam + ell;
+            umax = fmaxf(umax, us);
+            ub[s] = us;
+            if (trace) D->t_ell[pe_base + s] = ell;
         }
-        bad |= (ell != ell);
-        const float us = lam + ell;
-        umax = fmaxf(umax, us);
-        u[pe_base + s] = us;
-        if (trace) {
-            D->t_src[pe_base + s] = (int64_t)sb;
-            D->t_lam[pe_base + s] = lam;
-            D->t_ell[pe_base + s] = ell;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) D->t_prop[(size_t)c * N + pe_base + s] = x[c];
-        }
+        if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
     }
-    if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
     __syncthreads();   // wave maxima; u and the propagated particles stored
-    float lstar = L.wmax[0];
-    for (uint32_t w = 1; w < nwaves; ++w) lstar = fmaxf(lstar, L.wmax[w]);
+    float lstar = L.wmax[w_first];
+    for (uint32_t w = 1; w < wpp; ++w) lstar = fmaxf(lstar, L.wmax[w_first + w]);
 
     // ---- pass B (step 6 and the totals of step 7)
-    const uint32_t chunk = (np + nwaves * kWave - 1) / (nwaves * kWave) * kWave;
-    const uint32_t c_lo = wave * chunk;
-    const uint32_t c_hi = c_lo + chunk < np ? c_lo + chunk : np;   // may be <= c_lo
+    const uint32_t wi = wave - w_first;
+    const uint32_t chunk = (np + wpp * kWave - 1) / (wpp * kWave) * kWave;
+    const uint32_t c_lo = wi * chunk;
+    const uint32_t c_hi = active ? (c_lo + chunk < np ? c_lo + chunk : np) : 0u;   // may be <= c_lo
     const float qmaxf = (float)a.qmax;
     double sums[6] = {0, 0, 0, 0, 0, 0};
     uint32_t tot = 0;
@@ -189,7 +235,7 @@ __global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
         const uint32_t s = base + lane;
         if (s < c_hi) {
             float w;
-            const uint32_t Q = stream_q(u[pe_base + s], lstar, qmaxf, w);
+            const uint32_t Q = stream_q(ub[s], lstar, qmaxf, w);
             tot += Q;
             const double wd = (double)w;
             sums[0] += wd;
@@ -207,21 +253,22 @@ __global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
     }
     __syncthreads();   // wave totals
     uint32_t carry = 0, T = 0;
-    for (uint32_t w = 0; w < nwaves; ++w) {
-        if (w < wave) carry += L.wq[w];
-        T += L.wq[w];
+    for (uint32_t w = 0; w < wpp; ++w) {
+        if (w < wi) carry += L.wq[w_first + w];
+        T += L.wq[w_first + w];
     }
     const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
 
     // ---- pass C (step 7): ancestors of the output ranks
-    if (a.force_anc) {   // replay of another run's choices (test support)
-        for (uint32_t j = tid; j < np; j += B) {
+    if (!active) {
+    } else if (a.force_anc) {   // replay of another run's choices (test support)
+        for (uint32_t j = lt; j < np; j += tp) {
             const uint32_t anc = a.force_anc[pe_base + j];
             a.aout[pe_base + j] = (uint16_t)anc;
             if (trace) D->t_anc[pe_base + j] = anc;
         }
     } else if (T == 0) {   // no weight anywhere: every rank takes slot 0, as in k_step
-        for (uint32_t j = tid; j < np; j += B) {
+        for (uint32_t j = lt; j < np; j += tp) {
             a.aout[pe_base + j] = 0;
             if (trace) D->t_anc[pe_base + j] = 0;
         }
@@ -230,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
         for (uint32_t base = c_lo; base < c_hi; base += kWave) {
             const uint32_t s = base + lane;
             float w;
-            const uint32_t Q = (s < c_hi) ? stream_q(u[pe_base + s], lstar, qmaxf, w) : 0u;
+            const uint32_t Q = (s < c_hi) ? stream_q(ub[s], lstar, qmaxf, w) : 0u;
             const uint32_t incl = wave_incl_scan_u32(Q);
             // first rank of this lane's slot; non-decreasing over the lanes
             const uint32_t j0 = first_offspring(carry + incl - Q, np, T, V, inv_T);
@@ -254,24 +301,51 @@ __global__ __launch_bounds__(1024) void k_step_stream(StepArgs a, float *u) {
         }
     }
 
-    // ---- steps 8-9: the PE record
+    // ---- steps 8-9: the records of the group's PEs, all by thread 0 (the
+    // wave totals they need are in LDS since the last barrier)
     if (tid == 0) {
-        double t6[6] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t w = 0; w < nwaves; ++w)
-            for (int c = 0; c < 6; ++c) t6[c] += L.wsum[w * 6 + c];
-        pf_pe_record rec;
-        rec.log_mass = (lstar == -INFINITY) ? -INFINITY : (double)lstar + log(t6[0]);
-        for (int c = 0; c < 5; ++c) rec.xhat[c] = t6[1 + c] / t6[0];
-        rec.lstar = lstar;
-        rec.total_q = T;
-        a.rout[bid] = rec;
-        if (m == 0) {
-            a.nex_used[f] = p.nex;
-            if (a.nex_rec) a.nex_rec[f] = p.nex;
+        for (uint32_t q = 0; q < ppw && m0 + q < M; ++q) {
+            const uint32_t mq = m0 + q, wq0 = q * wpp;
+            double t6[6] = {0, 0, 0, 0, 0, 0};
+            float ls = L.wmax[wq0];
+            uint32_t Tq = 0;
+            for (uint32_t w = 0; w < wpp; ++w) {
+                for (int c = 0; c < 6; ++c) t6[c] += L.wsum[(wq0 + w) * 6 + c];
+                ls = fmaxf(ls, L.wmax[wq0 + w]);
+                Tq += L.wq[wq0 + w];
+            }
+            pf_pe_record rec;
+            rec.log_mass = (ls == -INFINITY) ? -INFINITY : (double)ls + log(t6[0]);
+            for (int c = 0; c < 5; ++c) rec.xhat[c] = t6[1 + c] / t6[0];
+            rec.lstar = ls;
+            rec.total_q = Tq;
+            a.rout[f * M + mq] = rec;
+            const Prologue *pq = L.pro + q;
+            if (mq == 0) {
+                a.nex_used[f] = pq->nex;
+                if (a.nex_rec) a.nex_rec[f] = pq->nex;
+            }
+            if (trace) {
+                D->t_pred[f * M + mq] = pq->pred;
+                D->t_v[f * M + mq] =
+                    mulshift(philox(mq, a.k, f, kTagResample << 24, a.key0, a.key1).x, Tq);
+            }
         }
-        if (trace) {
-            D->t_pred[bid] = p.pred;
-            D->t_v[bid] = V;
+    }
+    if (a.mout) {
+        // the last workgroup of the filter to publish its records computes the
+        // master step of this iteration (records made visible by the fence
+        // before the arrival count; the counter is reset for the next one)
+        if (tid == 0) {
+            __threadfence();
+            *L.flag = (atomicAdd(&a.arrive[f], 1u) == G - 1) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (*L.flag) {
+            __threadfence();
+            master_block(a.rout + (size_t)f * M, M, np, a.mode, a.fixed_nex, a.cutoff_ppm,
+                         L.wsum, a.mout + f);
+            if (tid == 0) atomicExch(&a.arrive[f], 0u);
         }
     }
 }

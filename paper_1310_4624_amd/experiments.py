@@ -89,16 +89,20 @@ def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int =
 
 
 def scaling(mode: str, n_pe: int, total: int = 1 << 20, steps: int = 30, warmup: int = 5,
-            seq=None) -> dict:
+            seq=None, tune: bool = False, **shape) -> dict:
     """GPU time per iteration with `total` particles over n_pe PEs (one spot,
-    512^2, every particle starting at the truth)."""
+    512^2, every particle starting at the truth); shape: block_size /
+    pes_per_wg, or tune=True for the autotuner's choice."""
     import torch
     wl = "arna_grad_512_256x4096"
     mflag, ratio = MODES[mode]
     cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, n_pe=n_pe,
-                              n_per_pe=total // n_pe)
+                              n_per_pe=total // n_pe, **shape)
     seq = seq if seq is not None else synth.make_sequence(wl, seed=1000, frames=warmup + steps)
     frames = _frames(seq)
+    if tune:
+        from . import autotune
+        cfg.update(autotune.tune(cfg, seq.initial_truth()[:1], frames, steps=6))
     tr = Tracker(cfg, seq.initial_truth()[:1])
     tr.run(frames[:warmup])
     torch.cuda.synchronize()
@@ -108,6 +112,7 @@ def scaling(mode: str, n_pe: int, total: int = 1 << 20, steps: int = 30, warmup:
     ks = warmup + 1 + np.arange(steps)
     ring = (ks - 1) % 64 == 0 if mflag == 1 else np.zeros(steps, bool)
     return dict(mode=mode, n_pe=n_pe, n_per_pe=total // n_pe, total=total,
+                block_size=cfg.get("block_size", 0), pes_per_wg=cfg.get("pes_per_wg", 0),
                 us_per_step=float(ms[~ring].mean() * 1e3), n_ex=int(est["n_ex"][0]))
 
 
@@ -116,7 +121,8 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
     """The batched workload: n_seq independent sequences of uneven size run
     (a) one after another, one launch per sequence and iteration, (b) as one
     batch (one launch per kernel variant and iteration), (c) the batch as HIP
-    graphs, (d) (b) and (c) with the workgroup sizes chosen by the autotuner.
+    graphs, (d) (b) and (c) with the launch shapes (workgroup size, PEs per
+    workgroup) chosen by the autotuner.
     Like a serving loop, (b) and (c) take the frames in calls of `call`
     iterations: the first call (untimed) loads the kernels and, in (c),
     captures the graph of a `call`-iteration run, which the timed calls
@@ -140,12 +146,12 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    def make(block_sizes=None):
-        return [Tracker(dict(c, block_size=(block_sizes[i] if block_sizes else 0)), t)
+    def make(shapes=None):
+        return [Tracker(dict(c, **(shapes[i] if shapes else {})), t)
                 for i, (c, t, _) in enumerate(seqs)]
 
-    def batched(block_sizes, graph):
-        trs = make(block_sizes)
+    def batched(shapes, graph):
+        trs = make(shapes)
         b = Batch(trs)
         b.run([d[:call] for d in dev], graph=graph)
         ms = timed(lambda: [b.run([d[t0:t0 + call] for d in dev], graph=graph)
@@ -178,10 +184,10 @@ def batch(frames: int = 20, n_seq: int = 64, tune: bool = True, seed: int = 2000
         out[name] = ms
         out[name.replace("_ms", "_equal")] = all(np.array_equal(a, r) for a, r in zip(x, ref))
     if tune:
-        blocks = [autotune.tune(c, t, d, steps=min(6, frames - 2)) for (c, t, _), d in zip(seqs, dev)]
+        shapes = [autotune.tune(c, t, d, steps=min(6, frames - 2)) for (c, t, _), d in zip(seqs, dev)]
         for name, graph in (("batched_tuned_ms", False), ("batched_graph_tuned_ms", True)):
-            out[name], _ = batched(blocks, graph)
-        out["tuned_block_sizes"] = blocks
+            out[name], _ = batched(shapes, graph)
+        out["tuned_shapes"] = [[s["block_size"], s["pes_per_wg"]] for s in shapes]
         out["default_block_sizes"] = [min(1024, (c["n_per_pe"] + 63) // 64 * 64) for c, _, _ in seqs]
     for k in list(out):
         if k.endswith("_ms"):
@@ -260,6 +266,9 @@ def main():
     ap.add_argument("--n-per-pe", type=int, default=4096)
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--curves", action="store_true", help="include the per-step curves")
+    ap.add_argument("--tuned", action="store_true",
+                    help="scaling: also the autotuner's launch shape (workgroup size, PEs per "
+                         "workgroup)")
     args = ap.parse_args()
     out = []
     if args.what == "infoshare-study":
@@ -305,6 +314,8 @@ def main():
         for n_pe in (256, 512, 1024, 2048, 4096, 8192):
             for mode in args.modes.split(","):
                 print(json.dumps(scaling(mode, n_pe)), flush=True)
+                if args.tuned:
+                    print(json.dumps(scaling(mode, n_pe, tune=True)), flush=True)
         return
     for s in range(args.seeds):
         for mode in args.modes.split(","):

@@ -12,13 +12,13 @@ from . import _native as nat
 CONFIG_KEYS = ("n_filters", "n_pe", "n_per_pe", "width", "height", "patch", "mode",
                "init_mode", "lik_mode", "fixed_ratio", "initial_ratio", "eff_cutoff",
                "psf_sigma", "background", "noise_sigma", "q", "sigma_I", "seed", "ring_groups",
-               "block_size", "launch")
+               "block_size", "launch", "pes_per_wg")
 
 DEFAULTS = dict(n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, patch=9,
                 mode=nat.PF_MODE_RNA, init_mode=nat.PF_INIT_TRACKING, lik_mode=nat.PF_LIK_PATCH,
                 fixed_ratio=0.1, initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5,
                 background=5.0, noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=1, ring_groups=0,
-                block_size=0, launch=nat.PF_LAUNCH_AUTO)
+                block_size=0, launch=nat.PF_LAUNCH_AUTO, pes_per_wg=0)
 
 
 TRAJ_RECORD_BYTES = ctypes.sizeof(nat.pf_master_t)

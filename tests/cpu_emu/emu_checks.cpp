@@ -5,11 +5,12 @@
 //                  iterations, one graph replayed) or pf_batch_run_noalloc
 //                  (2); results compared bit for bit
 //   traj           pf_run_traj's rows against pf_estimate after each step
-//   stream         the streaming step kernel (N_p > PF_MAX_PER_PE_LDS) against
-//                  k_step on PEs both can run, every traced output compared
-//                  after each iteration; then contexts of up to 65536
-//                  particles per PE through pf_step, their ancestors checked
-//                  against systematic resampling of the traced weights
+//   stream         k_step_flex against k_step on PEs both can run (one PE
+//                  per workgroup with the log-weights in HBM, and several PEs
+//                  per workgroup through pes_per_wg), every traced output
+//                  compared after each iteration; then contexts of up to
+//                  65536 particles per PE through pf_step, their ancestors
+//                  checked against systematic resampling of the traced weights
 #include "src/arna.hip"
 #include <algorithm>
 #include <random>
@@ -253,16 +254,19 @@ static int traj_main() {
     return bad ? 2 : 0;
 }
 
-// One iteration of context c by the streaming kernel, whatever its N_p.
-static int launch_stream(pf_ctx *c, const float *frame, float *u) {
+// One iteration of context c by k_step_flex with ppw PEs per workgroup of B
+// threads, log-weights in LDS (ulds) or in u.
+static int launch_flex(pf_ctx *c, const float *frame, float *u, uint32_t ppw, uint32_t B,
+                       bool ulds) {
     const uint64_t k = c->step + 1;
     int rc = ensure_ring(c, k);
     if (rc != PF_OK) return rc;
     StepArgs a = make_args(c, k, frame);
-    void *fn = pick_stream_kernel(c->half, c->cfg.lik_mode);
-    void *args[] = {&a, &u};
-    if (hipLaunchKernel(fn, dim3((uint32_t)c->FM), dim3(kStreamBlock), args, stream_lds_bytes(),
-                        c->stream) != hipSuccess)
+    void *fn = pick_flex_kernel(c->half, c->cfg.lik_mode, ulds);
+    void *args[] = {&a, &u, &ppw};
+    const uint32_t grid = c->cfg.n_filters * ((c->cfg.n_pe + ppw - 1) / ppw);
+    if (hipLaunchKernel(fn, dim3(grid), dim3(B), args,
+                        flex_lds_bytes(ulds ? ppw * c->cfg.n_per_pe : 0), c->stream) != hipSuccess)
         return PF_EHIP;
     advance(c, k);
     return PF_OK;
@@ -290,10 +294,86 @@ static std::vector<uint32_t> systematic(const uint32_t *q, uint32_t n, uint32_t 
     return anc;
 }
 
+// Iterations of context b (ppw = 0: through the library; else k_step_flex
+// launched directly) against context a (k_step), both from the same state
+// before every iteration: every traced value and the stored particles equal,
+// the records within FP64 summation order.
+static int compare_with_k_step(const Case &cs, uint32_t ppw_cfg, uint32_t block_cfg,
+                               uint32_t ppw_direct, bool ulds, std::mt19937_64 &rng) {
+    const int K = 5;
+    Inputs in = make_inputs(cs, K, rng);
+    float *d, *u;
+    hipMalloc(&d, in.frames.size() * 4);
+    memcpy(d, in.frames.data(), in.frames.size() * 4);
+    pf_config cfg = make_cfg(cs);
+    cfg.debug = PF_DEBUG_TRACE;
+    pf_ctx *a, *b;
+    check(pf_init(&cfg, in.truth.data(), &a), "init a");
+    cfg.pes_per_wg = ppw_cfg;
+    cfg.block_size = block_cfg;
+    check(pf_init(&cfg, in.truth.data(), &b), "init b");
+    hipMalloc(&u, b->N * 4);
+    int diff = 0;
+    double worst = 0;
+    for (int k = 0; k < K; ++k) {
+        check(launch_step(a, d + k * in.stride), "k_step");
+        if (ppw_direct)
+            check(launch_flex(b, d + k * in.stride, u, ppw_direct, 1024, ulds), "k_step_flex");
+        else
+            check(launch_step(b, d + k * in.stride), "k_step_flex via the library");
+        hipDeviceSynchronize();
+        const size_t N = a->N;
+        diff += memcmp(a->prop[a->cur], b->prop[b->cur], 5 * N * 4) != 0;
+        diff += memcmp(a->anc[a->cur], b->anc[b->cur], N * 2) != 0;
+        const int exact[] = {PF_DBG_RING, PF_DBG_NEX, PF_DBG_SRC, PF_DBG_PROP, PF_DBG_ELL,
+                             PF_DBG_Q, PF_DBG_ANCESTORS, PF_DBG_V, PF_DBG_LAMBDA};
+        for (int w : exact) {
+            std::vector<unsigned char> x = dbg<unsigned char>(a, w), y = dbg<unsigned char>(b, w);
+            if (x != y) {
+                fprintf(stderr, "np=%u step %d: debug buffer %d differs\n", cs.np, k, w);
+                ++diff;
+            }
+        }
+        for (uint64_t i = 0; i < a->FM; ++i) {
+            const pf_pe_record &ra = a->rec[a->cur][i], &rb = b->rec[b->cur][i];
+            diff += ra.lstar != rb.lstar || ra.total_q != rb.total_q;
+            const double dl = fabs(ra.log_mass - rb.log_mass);
+            worst = dl > worst ? dl : worst;
+            diff += !(dl <= 1e-12 * (1 + fabs(ra.log_mass)));
+            for (int c = 0; c < 5; ++c) {
+                const double dx = fabs(ra.xhat[c] - rb.xhat[c]);
+                worst = dx > worst ? dx : worst;
+                diff += !(dx <= 1e-12 * (1 + fabs(ra.xhat[c])));
+            }
+        }
+        if (a->mrec[0]) {   // the once-per-filter master records, within FP64 order
+            for (uint32_t f = 0; f < cs.F; ++f) {
+                const MasterRec &x = a->mrec[a->cur][f], &y = b->mrec[b->cur][f];
+                diff += x.nex_next != y.nex_next ||
+                        !(fabs(x.lglob - y.lglob) <= 1e-12 * (1 + fabs(x.lglob)));
+            }
+            memcpy(b->mrec[b->cur], a->mrec[a->cur], cs.F * sizeof(MasterRec));
+        }
+        // the next iteration starts from the same records
+        memcpy(b->rec[b->cur], a->rec[a->cur], a->FM * sizeof(pf_pe_record));
+    }
+    fprintf(stderr, "F=%u M=%u np=%u lik=%u, %s ppw=%u block=%u: %s (largest record difference %.3g)\n",
+            cs.F, cs.M, cs.np, cs.lik, ppw_direct ? (ulds ? "direct, u in LDS" : "direct, u in HBM")
+                                                  : "library",
+            ppw_direct ? ppw_direct : ppw_cfg, ppw_direct ? 1024 : b->block,
+            diff ? "DIFFERENT" : "same", worst);
+    pf_destroy(a);
+    pf_destroy(b);
+    hipFree(u);
+    hipFree(d);
+    return diff != 0;
+}
+
 static int stream_main() {
     int bad = 0;
     std::mt19937_64 rng(99);
-    // (1) the same iterations by both kernels, from the same state
+    // (1) the streaming form (one PE per workgroup, log-weights in HBM) on
+    // PEs k_step can run
     const Case same[] = {
         {1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 1},
         {2, 3, 1000, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 2},
@@ -302,60 +382,21 @@ static int stream_main() {
         {1, 4, 3000, 64, 64, 1, 0, 5, 0, 0, 0.1f, 5.f, 2.f, 5},
         {1, 1, 2000, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 6},
     };
-    for (const Case &cs : same) {
-        const int K = 5;
-        Inputs in = make_inputs(cs, K, rng);
-        float *d, *u;
-        hipMalloc(&d, in.frames.size() * 4);
-        memcpy(d, in.frames.data(), in.frames.size() * 4);
-        pf_config cfg = make_cfg(cs);
-        cfg.debug = PF_DEBUG_TRACE;
-        pf_ctx *a, *b;
-        check(pf_init(&cfg, in.truth.data(), &a), "init a");
-        check(pf_init(&cfg, in.truth.data(), &b), "init b");
-        hipMalloc(&u, b->N * 4);
-        int diff = 0;
-        double worst = 0;
-        for (int k = 0; k < K; ++k) {
-            check(launch_step(a, d + k * in.stride), "k_step");
-            check(launch_stream(b, d + k * in.stride, u), "k_step_stream");
-            hipDeviceSynchronize();
-            const size_t N = a->N;
-            diff += memcmp(a->prop[a->cur], b->prop[b->cur], 5 * N * 4) != 0;
-            diff += memcmp(a->anc[a->cur], b->anc[b->cur], N * 2) != 0;
-            const int exact[] = {PF_DBG_RING, PF_DBG_NEX, PF_DBG_SRC, PF_DBG_PROP, PF_DBG_ELL,
-                                 PF_DBG_Q, PF_DBG_ANCESTORS, PF_DBG_V};
-            for (int w : exact) {
-                std::vector<unsigned char> x = dbg<unsigned char>(a, w), y = dbg<unsigned char>(b, w);
-                if (x != y) {
-                    fprintf(stderr, "np=%u step %d: debug buffer %d differs\n", cs.np, k, w);
-                    ++diff;
-                }
-            }
-            for (uint64_t i = 0; i < a->FM; ++i) {
-                const pf_pe_record &ra = a->rec[a->cur][i], &rb = b->rec[b->cur][i];
-                diff += ra.lstar != rb.lstar || ra.total_q != rb.total_q;
-                const double dl = fabs(ra.log_mass - rb.log_mass);
-                worst = dl > worst ? dl : worst;
-                diff += !(dl <= 1e-12 * (1 + fabs(ra.log_mass)));
-                for (int c = 0; c < 5; ++c) {
-                    const double dx = fabs(ra.xhat[c] - rb.xhat[c]);
-                    worst = dx > worst ? dx : worst;
-                    diff += !(dx <= 1e-12 * (1 + fabs(ra.xhat[c])));
-                }
-            }
-            // the next iteration starts from the same records
-            memcpy(b->rec[b->cur], a->rec[a->cur], a->FM * sizeof(pf_pe_record));
-        }
-        fprintf(stderr, "np=%u M=%u lik=%u: %s (largest record difference %.3g)\n", cs.np, cs.M,
-                cs.lik, diff ? "DIFFERENT" : "same", worst);
-        bad += diff != 0;
-        pf_destroy(a);
-        pf_destroy(b);
-        hipFree(u);
-        hipFree(d);
-    }
-    // (2) contexts beyond the LDS stage, through the library
+    for (const Case &cs : same) bad += compare_with_k_step(cs, 0, 0, 1, false, rng);
+    // (2) several PEs per workgroup, through the library (pes_per_wg)
+    struct Grouped { Case cs; uint32_t ppw, block; };
+    const Grouped grouped[] = {
+        {{1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 21}, 2, 0},
+        {{1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 22}, 4, 512},
+        {{3, 5, 77, 128, 128, 0, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 23}, 3, 0},     // a partial last group
+        {{2, 8, 300, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 24}, 8, 0},
+        {{1, 6, 1000, 64, 48, 1, 2, 9, 0, 0, 0.1f, 10.f, 2.f, 25}, 4, 0},
+        {{1, 3, 200, 64, 64, 1, 0, 7, 0, 0, 0.1f, 5.f, 2.f, 26}, 2, 0},
+        {{1, 2100, 64, 96, 80, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 27}, 16, 0},  // master record
+        {{2, 7, 130, 96, 80, 1, 0, 9, 0, 4, 0.1f, 5.f, 2.f, 28}, 5, 640},   // grouped ring
+    };
+    for (const Grouped &g : grouped) bad += compare_with_k_step(g.cs, g.ppw, g.block, 0, true, rng);
+    // (3) contexts beyond the LDS stage, through the library
     const Case big[] = {
         {1, 2, 5000, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},
         {2, 3, 8192, 96, 96, 0, 2, 9, 1024, 0, 0.5f, 10.f, 2.f, 12},

@@ -51,6 +51,7 @@ int main(void) {
   printf("%zu %zu\\n", offsetof(pf_estimate_t, step), offsetof(pf_pe_record, lstar));
   printf("%zu %zu %zu\\n", sizeof(pf_master_t), offsetof(pf_master_t, n_ex),
          offsetof(pf_master_t, step));
+  printf("%zu\\n", offsetof(pf_config, pes_per_wg));
   return 0;
 }
 """)
@@ -64,7 +65,8 @@ int main(void) {
             nat.pf_config.fixed_ratio.offset, nat.pf_config.debug.offset,
             nat.pf_config.seed.offset, nat.pf_config.stream.offset,
             nat.pf_estimate_t.step.offset, nat.pf_pe_record.lstar.offset,
-            ctypes.sizeof(nat.pf_master_t), nat.pf_master_t.n_ex.offset, nat.pf_master_t.step.offset]
+            ctypes.sizeof(nat.pf_master_t), nat.pf_master_t.n_ex.offset, nat.pf_master_t.step.offset,
+            nat.pf_config.pes_per_wg.offset]
     assert got == want
 
 
@@ -114,6 +116,14 @@ def _init(L, **kw):
     (dict(n_per_pe=5000, debug=nat.PF_DEBUG_LINEAGE), nat.PF_EUNSUPPORTED),
     (dict(n_per_pe=5000, launch=nat.PF_LAUNCH_PERSISTENT), nat.PF_EUNSUPPORTED),
     (dict(n_per_pe=8192, n_pe=2048), nat.PF_EUNSUPPORTED),
+    # several PEs per workgroup: whole waves per PE, 4 slots per thread at most
+    (dict(pes_per_wg=17), nat.PF_EINVAL),
+    (dict(n_per_pe=5000, pes_per_wg=2), nat.PF_EINVAL),
+    (dict(n_per_pe=256, pes_per_wg=4, block_size=640), nat.PF_EINVAL),   # 160 threads per PE
+    (dict(n_per_pe=600, pes_per_wg=8, block_size=1024), nat.PF_EINVAL),  # 128 x 4 < 600
+    (dict(n_per_pe=1024, pes_per_wg=16), nat.PF_EINVAL),                 # 64 x 4 < 1024
+    (dict(n_per_pe=256, pes_per_wg=4, debug=nat.PF_DEBUG_LINEAGE), nat.PF_EUNSUPPORTED),
+    (dict(n_per_pe=256, pes_per_wg=4, launch=nat.PF_LAUNCH_PERSISTENT), nat.PF_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_config_on_host(L, bad, code):
     assert _init(L, **bad) == code

@@ -125,7 +125,7 @@ def test_autotuner_and_batched_workload():
     seqs = synth.batch_sequences(seed=7, n_seq=3, frames=8)
     c, t, fr = seqs[0]
     b = autotune.tune(c, t, torch.from_numpy(fr).cuda(), steps=4)
-    assert b in autotune.candidates(c["n_per_pe"])
+    assert (b["block_size"], b["pes_per_wg"]) in autotune.shapes(c["n_per_pe"], c["n_pe"])
     out = batch(frames=6, n_seq=4, seed=7)
     assert out["batched_equal"] and out["batched_graph_equal"]
-    assert len(out["tuned_block_sizes"]) == 4
+    assert len(out["tuned_shapes"]) == 4

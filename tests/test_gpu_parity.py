@@ -197,6 +197,17 @@ def seeded_case(name):
         state = synth.random_state(rng, F, M, n_p, side, side, spread=spread,
                                    centre=truth[0, :, :2], I0=10.0)
         return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (F, M))
+    elif name == "full_scaling_8192x128":
+        # the strong-scaling end point at 2^20: 8192 PEs of 128 particles, one
+        # spot, particles around it (the launch the scaling experiment times
+        # with several PEs per workgroup)
+        cfg = synth.filter_config("arna_grad_512_256x4096", seed=SEED + 13, n_pe=8192,
+                                  n_per_pe=128)
+        seq = synth.make_sequence("arna_grad_512_256x4096", seed=1004, frames=3)
+        frame = seq.frames[2]
+        state = synth.random_state(rng, 1, 8192, 128, cfg["width"], cfg["height"], spread=1.5,
+                                   centre=seq.truth[3, :1, :2], I0=10.0)
+        return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (1, 8192))
     elif name == "poisson_rna_1x2x20000":
         # ragged streaming PEs (20000 = 312 x 64 + 32) exchanging half their slots
         cfg = dict(n_filters=1, n_pe=2, n_per_pe=20000, width=128, height=96, patch=9,
@@ -277,9 +288,20 @@ def test_one_step_parity_2e24():
     check_one_step("full_tracking_64x64x4096", 7)
 
 
-def check_one_step(name, k_done):
-    print(f"one-step parity {name} k_done={k_done}", flush=True)
+@pytest.mark.parametrize("name,ppw", [("rna_128_4x256", 4), ("arna_ragged_2x3x100", 2),
+                                      ("arna_2x2100x4", 16), ("poisson_arna_1x4x1000", 4),
+                                      ("point_rna_3x5x77", 3), ("arna_groups_2x24x300", 8),
+                                      ("full_scaling_8192x128", 16)])
+@pytest.mark.parametrize("k_done", [0, 7])
+def test_one_step_parity_grouped(name, ppw, k_done):
+    """Several PEs per workgroup (pes_per_wg), every PE."""
+    check_one_step(name, k_done, pes_per_wg=ppw)
+
+
+def check_one_step(name, k_done, **over):
+    print(f"one-step parity {name} k_done={k_done} {over}", flush=True)
     cfg, frame, state, logmass = seeded_case(name)
+    cfg = dict(cfg, **over)
     g, tr = run_one_step(cfg, frame, state, logmass, k_done)
     compare_one_step(cfg, frame, g, tr, k_done)
 
