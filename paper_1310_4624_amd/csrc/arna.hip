@@ -1312,23 +1312,28 @@ int batch_run_graph(pf_batch *b, const float *const *d_frames, const uint64_t *f
             }
             b->graphs.push_back({n, exec});
         }
+        // the contexts without a batched variant run beside the graph, spread
+        // over the workers; they are forked before the graph is launched (they
+        // depend only on the batch's earlier work) and joined after it
+        if (!b->solo.empty()) HIP_OK(hipEventRecord(b->ev_fork, b->stream));
         if (exec) HIP_OK(hipGraphLaunch(exec, b->stream));
-        // the contexts without a batched variant, beside the graph
         if (!b->solo.empty()) {
-            hipStream_t w = b->workers[0];
-            HIP_OK(hipEventRecord(b->ev_fork, b->stream));
-            HIP_OK(hipStreamWaitEvent(w, b->ev_fork, 0));
+            const size_t used = b->solo.size() < nw ? b->solo.size() : nw;
+            for (size_t w = 0; w < used; ++w)
+                HIP_OK(hipStreamWaitEvent(b->workers[w], b->ev_fork, 0));
             int rc = PF_OK;
-            for (uint32_t i : b->solo) {
+            for (size_t si = 0; si < b->solo.size() && rc == PF_OK; ++si) {
+                const uint32_t i = b->solo[si];
                 pf_ctx *c = b->ctx[i];
-                c->stream = w;
+                c->stream = b->workers[si % nw];
                 for (uint32_t t = 0; t < n && rc == PF_OK; ++t)
                     rc = launch_step(c, d_frames[i] + (size_t)(done + t) * frame_stride[i]);
                 c->stream = b->stream;
             }
-            if (hipEventRecord(b->ev_join[0], w) != hipSuccess ||
-                hipStreamWaitEvent(b->stream, b->ev_join[0], 0) != hipSuccess)
-                rc = PF_EHIP;
+            for (size_t w = 0; w < used; ++w)
+                if (hipEventRecord(b->ev_join[w], b->workers[w]) != hipSuccess ||
+                    hipStreamWaitEvent(b->stream, b->ev_join[w], 0) != hipSuccess)
+                    rc = PF_EHIP;
             if (rc != PF_OK) return rc;
         }
         done += n;
