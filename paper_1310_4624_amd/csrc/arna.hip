@@ -73,6 +73,10 @@ struct pf_ctx {
     bool flex, streamk;
     uint32_t ppw, n_wg;
     float *u;
+    // streamed PEs split over seg_g workgroups each (three launches per
+    // iteration; the per-segment results live in sb)
+    bool split;
+    SplitBufs sb;
     float *prop[2];
     uint16_t *anc[2];
     pf_pe_record *rec[2];
@@ -275,11 +279,51 @@ void *pick_flex_kernel(uint32_t half, uint32_t lik_mode, bool ulds) {
                 : pick_flex_kernel_u<false>(half, lik_mode);
 }
 
-// The one-iteration kernel of a context.
+template <int HALF, int LIK>
+void *split_kernel() {
+    return reinterpret_cast<void *>(&k_split_weights<HALF, LIK>);
+}
+
+template <int LIK>
+void *pick_split_patch_kernel(uint32_t half) {
+    switch (half) {
+        case 0: return split_kernel<0, LIK>();
+        case 1: return split_kernel<1, LIK>();
+        case 2: return split_kernel<2, LIK>();
+        case 3: return split_kernel<3, LIK>();
+        case 4: return split_kernel<4, LIK>();
+        case 5: return split_kernel<5, LIK>();
+        case 6: return split_kernel<6, LIK>();
+        case 7: return split_kernel<7, LIK>();
+        default: return nullptr;
+    }
+}
+
+void *split_totals_kernel() { return reinterpret_cast<void *>(&k_split_totals); }
+void *split_ancestors_kernel() { return reinterpret_cast<void *>(&k_split_ancestors); }
+
+// The first of the three launches of a split iteration.
+void *pick_split_kernel(uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT) return split_kernel<0, kLikPoint>();
+    if (lik_mode == PF_LIK_POISSON) return pick_split_patch_kernel<kLikPoisson>(half);
+    return pick_split_patch_kernel<kLikGauss>(half);
+}
+
+// The one-iteration kernel of a context (for a split context, the first of
+// its three launches).
 void *ctx_step_kernel(const pf_ctx *c) {
+    if (c->split) return pick_split_kernel(c->half, c->cfg.lik_mode);
     return c->flex ? pick_flex_kernel(c->half, c->cfg.lik_mode, !c->streamk)
                    : pick_step_kernel(c->ppt, c->half, c->cfg.lik_mode);
 }
+
+// Streamed PEs are split over several workgroups while a context has fewer
+// PEs than compute units (with one workgroup per PE most would sit idle).
+// Measured on MI355X (tracking frames, us per iteration, split / one
+// workgroup per PE): 16 x 65536 48.5 / 275, 64 x 16384 43.2 / 91.4,
+// 2 x 3 x 20000 33.0 / 102.5, 256 x 8192 70.7 / 61.9, 512 x 8192 124.9 / 118.6.
+constexpr uint64_t kSplitBelowPEs = 256;
+bool split_pes(uint64_t FM) { return FM < kSplitBelowPEs; }
 
 // Threads per PE of a context with several PEs per workgroup: N_p rounded up
 // to 64, at most 1024 / ppw (rounded down to 64).
@@ -401,7 +445,8 @@ void free_all(pf_ctx *c) {
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
                     c->mrec[0], c->mrec[1], c->arrive, c->bar, c->run_args,
                     c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
-                    c->g_lbar[1], c->g_theta, c->g_out, c->u};
+                    c->g_lbar[1], c->g_theta, c->g_out, c->u, c->sb.seg_max, c->sb.seg_wq,
+                    c->sb.seg_sum};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -483,7 +528,8 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame, pf_master_t *traj_
     a.lin_in = (uint32_t)c->cur;
     a.err = c->err;
     a.nex_used = c->nex_used;
-    a.traj_prev = c->mrec[0] ? nullptr : traj_prev;   // (many PEs: k_global writes the rows)
+    // (many PEs or split PEs: k_global writes the rows)
+    a.traj_prev = (c->mrec[0] || c->split) ? nullptr : traj_prev;
     return a;
 }
 
@@ -518,6 +564,18 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
     StepArgs a = make_args(c, k, frame, traj_prev);
     void *fn = ctx_step_kernel(c);
     if (!fn) return PF_EUNSUPPORTED;
+    if (c->split) {
+        // three launches, the segments of every PE side by side
+        void *sargs[] = {&a, &c->sb};
+        const dim3 grid((uint32_t)(c->FM * c->sb.G)), blk(kSplitBlock);
+        HIP_OK(hipLaunchKernel(fn, grid, blk, sargs, split_lds_bytes(), c->stream));
+        HIP_OK(hipLaunchKernel(split_totals_kernel(), grid, blk, sargs, split_lds_bytes(),
+                               c->stream));
+        HIP_OK(hipLaunchKernel(split_ancestors_kernel(), grid, blk, sargs, split_lds_bytes(),
+                               c->stream));
+        advance(c, k);
+        return PF_OK;
+    }
     void *args[] = {&a, &c->u, &c->ppw};   // (k_step takes the first only)
     HIP_OK(hipLaunchKernel(fn, dim3(c->n_wg), dim3(c->block), args, c->lds, c->stream));
     advance(c, k);
@@ -612,7 +670,7 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
         const float *frame = frames + (size_t)done * stride;
         if (len == 1) {
             const size_t F = c->cfg.n_filters;
-            const bool fused = traj && !c->mrec[0];
+            const bool fused = traj && !c->mrec[0] && !c->split;
             rc = launch_step(c, frame, (fused && done) ? traj + (size_t)(done - 1) * F : nullptr);
             if (rc == PF_OK && traj && !fused) rc = launch_global(c, traj + (size_t)done * F);
         } else {
@@ -714,6 +772,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->FM = (uint64_t)F * M;
     c->N = c->FM * np;
     c->streamk = np > PF_MAX_PER_PE_LDS;
+    c->split = c->streamk && split_pes(c->FM);
     c->ppw = cfg->pes_per_wg > 1 ? cfg->pes_per_wg : 1;
     c->flex = c->streamk || c->ppw > 1;
     c->n_wg = (uint32_t)((uint64_t)F * ((M + c->ppw - 1) / c->ppw));
@@ -773,6 +832,14 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     if (rc == PF_OK) rc = dev_alloc(&c->nex_used, F);
     if (rc == PF_OK) rc = dev_alloc(&c->est, F);
     if (rc == PF_OK && c->streamk) rc = dev_alloc(&c->u, N);
+    if (rc == PF_OK && c->split) {
+        c->sb.u = c->u;
+        c->sb.G = (np + kSplitSlots - 1) / kSplitSlots;
+        const size_t segs = (size_t)c->FM * c->sb.G;
+        rc = dev_alloc(&c->sb.seg_max, segs);
+        if (rc == PF_OK) rc = dev_alloc(&c->sb.seg_wq, segs * kSplitWaves);
+        if (rc == PF_OK) rc = dev_alloc(&c->sb.seg_sum, segs * 6);
+    }
     if (rc == PF_OK && trace) {
         rc = dev_alloc(&c->t_pred, c->FM);
         if (rc == PF_OK) rc = dev_alloc(&c->t_v, c->FM);

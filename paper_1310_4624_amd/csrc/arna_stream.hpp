@@ -86,6 +86,205 @@ __device__ __forceinline__ uint32_t uni(uint32_t v) {
 }
 __device__ __forceinline__ float uni(float v) { return __uint_as_float(uni(__float_as_uint(v))); }
 
+// The image tile of a workgroup: 64 x 64 pixels of z - B around the estimate
+// of k-1 moved one step (x + v), zero outside the image; off when the
+// estimate is not finite (a PE without mass).
+struct TileView {
+    int tx0, ty0;
+    bool on, inside;
+};
+template <bool POINT>
+__device__ __forceinline__ TileView load_tile(const StepArgs &a, const double *xh, float *tile,
+                                              const uint32_t tid, const uint32_t B) {
+    TileView v{0, 0, false, false};
+    if (POINT) return v;
+    const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
+    if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN
+        v.tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
+        v.ty0 = (int)floor(cy + 0.5) - kTileRows / 2;
+        v.on = v.tx0 < (int)a.lik.W && v.tx0 + kTileCols > 0 && v.ty0 < (int)a.lik.H &&
+               v.ty0 + kTileRows > 0;
+        v.inside = v.tx0 >= 0 && v.ty0 >= 0 && v.tx0 + kTileCols <= (int)a.lik.W &&
+                   v.ty0 + kTileRows <= (int)a.lik.H;
+    }
+    if (v.on)
+        for (uint32_t idx = tid; idx < (uint32_t)(kTileRows * kTileCols); idx += B) {
+            const int uu = v.tx0 + (int)(idx % kTileCols), vv = v.ty0 + (int)(idx / kTileCols);
+            const bool in = (unsigned)uu < (unsigned)a.lik.W && (unsigned)vv < (unsigned)a.lik.H;
+            tile[(idx / kTileCols) * kTilePitch + idx % kTileCols] =
+                in ? a.lik.img[(size_t)vv * a.lik.W + uu] - a.lik.bg : 0.f;
+        }
+    return v;
+}
+
+// The prologue's results, the same in every lane of a wave, to scalar registers.
+__device__ __forceinline__ Prologue uniform_prologue(const Prologue *pp) {
+    Prologue p = *pp;
+    p.pred = uni(p.pred);
+    p.nex = uni(p.nex);
+    p.c_own = uni(p.c_own);
+    p.c_pred = uni(p.c_pred);
+    p.lam_own = uni(p.lam_own);
+    p.lam_pred = uni(p.lam_pred);
+    return p;
+}
+
+// Pass A (steps 3-5) over slots s = s0, s0 + step, ... < s1 of PE (f, m):
+// the slot's particle (own, through its ancestor, or received), the normals,
+// propagation, the likelihood, u = lambda + l to ub[s].  Returns the lane's
+// maximum of u.  Called by whole waves (a NaN log-likelihood sets the sticky
+// error bit through a wave vote).
+template <int HALF, int LIK>
+__device__ __forceinline__ float pass_a(const StepArgs &a, const Prologue &p, uint32_t f,
+                                        uint32_t m, uint32_t s0, uint32_t s1, uint32_t step,
+                                        float *ub, const float *tile, const TileView &tv) {
+    constexpr int P = 2 * HALF + 1;
+    constexpr bool POINT = LIK == kLikPoint;
+    const uint32_t np = a.np, N = a.N;
+    const uint32_t pe_base = (f * a.M + m) * np, pred_base = (f * a.M + p.pred) * np;
+    const DebugBufs *D = a.dbg;
+    const bool trace = D && D->t_q;
+    float umax = -INFINITY;
+    bool bad = false;
+#pragma unroll 1
+    for (uint32_t s = s0; s < s1; s += step) {
+        const uint32_t r = received_from(s, p, np);
+        const uint32_t blk = (r == kNoSlot) ? pe_base : pred_base;   // PE whose slot it takes
+        const uint32_t sb = blk + ((r == kNoSlot) ? s : r);          // that resampled slot
+        const float lam = (r == kNoSlot) ? p.lam_own : p.lam_pred;
+        const uint32_t gsrc = blk + a.ain[sb];                         // its propagated particle
+        float x[5], e[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) x[c] = a.pin[(size_t)c * N + gsrc];
+        five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e);
+        propagate(x, e, a.dyn);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a.pout[(size_t)c * N + pe_base + s] = x[c];
+        if (trace) {
+            D->t_src[pe_base + s] = (int64_t)sb;
+            D->t_lam[pe_base + s] = lam;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) D->t_prop[(size_t)c * N + pe_base + s] = x[c];
+        }
+        float ell = 0.f;
+        int u0, v0;
+        if (POINT) {
+            ell = loglik_point(x, a.lik, f);
+        } else if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
+            const int du = u0 - tv.tx0, dv = v0 - tv.ty0;
+            if (tv.on && (unsigned)du <= (unsigned)(kTileCols - P) &&
+                (unsigned)dv <= (unsigned)(kTileRows - P)) {
+                const float *pix = tile + dv * kTilePitch + du;
+                if (LIK == kLikPoisson)
+                    ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, kTilePitch, a.lik);
+                else
+                    ell = tv.inside ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix,
+                                                                          kTilePitch, a.lik)
+                                    : patch_loglik<HALF, kFromTile>(x, u0, v0, pix, kTilePitch,
+                                                                    a.lik);
+            } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W && v0 + P <= (int)a.lik.H) {
+                const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
+                ell = (LIK == kLikPoisson)
+                          ? patch_loglik_poisson<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik)
+                          : patch_loglik<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik);
+            } else {
+                ell = (LIK == kLikPoisson)
+                          ? patch_loglik_poisson<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0,
+                                                                          a.lik)
+                          : patch_loglik<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0, a.lik);
+            }
+        }
+        bad |= (ell != ell);
+        const float us = lam + ell;
+        umax = fmaxf(umax, us);
+        ub[s] = us;
+        if (trace) D->t_ell[pe_base + s] = ell;
+    }
+    if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(a.err, 1u);
+    return umax;
+}
+
+// Pass B (step 6 and the totals of step 7) over the contiguous slots
+// [c_lo, c_hi) of the PE whose slots start at pe_base, 64 at a time: the
+// lane's total of Q and its FP64 sums (W, W x).
+__device__ __forceinline__ uint32_t pass_b(const StepArgs &a, const float *ub, uint32_t pe_base,
+                                           uint32_t c_lo, uint32_t c_hi, float lstar,
+                                           double (&sums)[6]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const DebugBufs *D = a.dbg;
+    const bool trace = D && D->t_q;
+    const float qmaxf = (float)a.qmax;
+    uint32_t tot = 0;
+    for (uint32_t base = c_lo; base < c_hi; base += kWave) {
+        const uint32_t s = base + lane;
+        if (s < c_hi) {
+            float w;
+            const uint32_t Q = stream_q(ub[s], lstar, qmaxf, w);
+            tot += Q;
+            const double wd = (double)w;
+            sums[0] += wd;
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                sums[1 + c] += wd * (double)a.pout[(size_t)c * a.N + pe_base + s];
+            if (trace) D->t_q[pe_base + s] = Q;
+        }
+    }
+    return tot;
+}
+
+// Pass C (step 7) over the same slots, by the whole wave: `carry` is the sum
+// of Q over the PE's slots before c_lo; writes the ancestors of the output
+// ranks these slots own.  T > 0.
+__device__ __forceinline__ void pass_c(const StepArgs &a, const float *ub, uint32_t pe_base,
+                                       uint32_t c_lo, uint32_t c_hi, float lstar, uint32_t carry,
+                                       uint32_t T, uint32_t V) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t np = a.np;
+    const DebugBufs *D = a.dbg;
+    const bool trace = D && D->t_q;
+    const float qmaxf = (float)a.qmax;
+    const double inv_T = 1.0 / (double)T;
+    for (uint32_t base = c_lo; base < c_hi; base += kWave) {
+        const uint32_t s = base + lane;
+        float w;
+        const uint32_t Q = (s < c_hi) ? stream_q(ub[s], lstar, qmaxf, w) : 0u;
+        const uint32_t incl = wave_incl_scan_u32(Q);
+        // first rank of this lane's slot; non-decreasing over the lanes
+        const uint32_t j0 = first_offspring(carry + incl - Q, np, T, V, inv_T);
+        carry += lane63(incl);
+        const uint32_t J0 = (uint32_t)__builtin_amdgcn_readlane((int)j0, 0);
+        const uint32_t J1 = first_offspring(carry, np, T, V, inv_T);   // wave-uniform
+        for (uint32_t r0 = J0; r0 < J1; r0 += kWave) {
+            const uint32_t r = r0 + lane;
+            // the last lane whose first rank is <= r owns rank r
+            uint32_t lo = 0;
+#pragma unroll
+            for (uint32_t step = kWave / 2; step >= 1; step /= 2) {
+                const uint32_t cand = lo + step;
+                if ((uint32_t)__shfl((int)j0, (int)cand) <= r) lo = cand;
+            }
+            if (r < J1) {
+                a.aout[pe_base + r] = (uint16_t)(base + lo);
+                if (trace) D->t_anc[pe_base + r] = base + lo;
+            }
+        }
+    }
+}
+
+// Step 7 when the choices are not drawn: replayed ancestors (test support) or,
+// with no weight anywhere, slot 0 for every rank (as k_step's marks give);
+// ranks j = j0, j0 + step, ... < j1.
+__device__ __forceinline__ void fixed_ancestors(const StepArgs &a, uint32_t pe_base, uint32_t j0,
+                                                uint32_t j1, uint32_t step) {
+    const DebugBufs *D = a.dbg;
+    const bool trace = D && D->t_q;
+    for (uint32_t j = j0; j < j1; j += step) {
+        const uint32_t anc = a.force_anc ? a.force_anc[pe_base + j] : 0u;
+        a.aout[pe_base + j] = (uint16_t)anc;
+        if (trace) D->t_anc[pe_base + j] = anc;
+    }
+}
+
 // ppw PEs of one filter per workgroup (tp = blockDim.x / ppw threads each, a
 // multiple of 64; workgroup g of filter f holds PEs g ppw .. g ppw + ppw - 1,
 // the last workgroup of a filter possibly fewer).  ULDS: the log-weights stay
@@ -94,10 +293,9 @@ __device__ __forceinline__ float uni(float v) { return __uint_as_float(uni(__flo
 template <int HALF, int LIK, bool ULDS>
 __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int P = 2 * HALF + 1;
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x;
-    const uint32_t M = a.M, np = a.np, N = a.N;
+    const uint32_t M = a.M, np = a.np;
     const uint32_t B = blockDim.x, tp = B / ppw;
     const uint32_t G = (M + ppw - 1) / ppw;   // workgroups per filter
     const uint32_t f = blockIdx.x / G, m0 = (blockIdx.x % G) * ppw;
@@ -115,107 +313,21 @@ __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, ui
     const bool trace = D && D->t_q;
 
     // ---- steps 1-2 (the first wave of each PE); the image tile around the
-    // estimate of k-1 of the group's first PE, moved one step (every thread)
+    // estimate of k-1 of the group's first PE (every thread)
     if (active && lt < kWave) {
         if (a.min)
             prologue_master(a, f, m, L.pro + lp, lane);
         else
             prologue_wave(a, f, m, L.pro + lp, lane);
     }
-    int tx0 = 0, ty0 = 0;
-    bool tile_on = false, tile_inside = false;
-    if (!POINT) {
-        const double *xh = a.rin[f * M + m0].xhat;
-        const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
-        if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN (a PE without mass)
-            tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
-            ty0 = (int)floor(cy + 0.5) - kTileRows / 2;
-            tile_on = tx0 < (int)a.lik.W && tx0 + kTileCols > 0 && ty0 < (int)a.lik.H &&
-                      ty0 + kTileRows > 0;
-            tile_inside = tx0 >= 0 && ty0 >= 0 && tx0 + kTileCols <= (int)a.lik.W &&
-                          ty0 + kTileRows <= (int)a.lik.H;
-        }
-        if (tile_on)
-            for (uint32_t idx = tid; idx < (uint32_t)(kTileRows * kTileCols); idx += B) {
-                const int uu = tx0 + (int)(idx % kTileCols), vv = ty0 + (int)(idx / kTileCols);
-                const bool in =
-                    (unsigned)uu < (unsigned)a.lik.W && (unsigned)vv < (unsigned)a.lik.H;
-                L.tile[(idx / kTileCols) * kTilePitch + idx % kTileCols] =
-                    in ? a.lik.img[(size_t)vv * a.lik.W + uu] - a.lik.bg : 0.f;
-            }
-    }
+    const TileView tv = load_tile<POINT>(a, a.rin[f * M + m0].xhat, L.tile, tid, B);
     __syncthreads();   // prologues and tile visible
 
     // ---- pass A (steps 3-5)
     float umax = -INFINITY;
     if (active) {
-        Prologue p = L.pro[lp];
-        p.pred = uni(p.pred);
-        p.nex = uni(p.nex);
-        p.c_own = uni(p.c_own);
-        p.c_pred = uni(p.c_pred);
-        p.lam_own = uni(p.lam_own);
-        p.lam_pred = uni(p.lam_pred);
-        const uint32_t pred_base = (f * M + p.pred) * np;
-        bool bad = false;
-#pragma unroll 1
-        for (uint32_t s = lt; s < np; s += tp) {
-            const uint32_t r = received_from(s, p, np);
-            const uint32_t blk = (r == kNoSlot) ? pe_base : pred_base;   // PE whose slot it takes
-            const uint32_t sb = blk + ((r == kNoSlot) ? s : r);          // that resampled slot
-            const float lam = (r == kNoSlot) ? p.lam_own : p.lam_pred;
-            const uint32_t gsrc = blk + a.ain[sb];                         // its propagated particle
-            float x[5], e[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) x[c] = a.pin[(size_t)c * N + gsrc];
-            five_normals(philox(m * np + s, a.k, f, kTagProp << 24, a.key0, a.key1), e);
-            propagate(x, e, a.dyn);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) a.pout[(size_t)c * N + pe_base + s] = x[c];
-            if (trace) {
-                D->t_src[pe_base + s] = (int64_t)sb;
-                D->t_lam[pe_base + s] = lam;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) D->t_prop[(size_t)c * N + pe_base + s] = x[c];
-            }
-            float ell = 0.f;
-            int u0, v0;
-            if (POINT) {
-                ell = loglik_point(x, a.lik, f);
-            } else if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
-                const int du = u0 - tx0, dv = v0 - ty0;
-                if (tile_on && (unsigned)du <= (unsigned)(kTileCols - P) &&
-                    (unsigned)dv <= (unsigned)(kTileRows - P)) {
-                    const float *pix = L.tile + dv * kTilePitch + du;
-                    if (LIK == kLikPoisson)
-                        ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, kTilePitch,
-                                                                     a.lik);
-                    else
-                        ell = tile_inside ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix,
-                                                                                kTilePitch, a.lik)
-                                          : patch_loglik<HALF, kFromTile>(x, u0, v0, pix,
-                                                                          kTilePitch, a.lik);
-                } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W &&
-                           v0 + P <= (int)a.lik.H) {
-                    const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
-                    ell = (LIK == kLikPoisson)
-                              ? patch_loglik_poisson<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik)
-                              : patch_loglik<HALF, kFromImage>(x, u0, v0, pix, 0, a.lik);
-                } else {
-                    ell = (LIK == kLikPoisson)
-                              ? patch_loglik_poisson<HALF, kFromImageBorder>(x, u0, v0, a.lik.img,
-                                                                              0, a.lik)
-                              : patch_loglik<HALF, kFromImageBorder>(x, u0, v0, a.lik.img, 0,
-                                                                     a.lik);
-                }
-            }
-            bad |= (ell != ell);
-            const float us = lam + ell;
-            umax = fmaxf(umax, us);
-            ub[s] = us;
-            if (trace) D->t_ell[pe_base + s] = ell;
-        }
-        if (__any(bad) && lane == 0) atomicOr(a.err, 1u);
+        const Prologue p = uniform_prologue(L.pro + lp);
+        umax = pass_a<HALF, LIK>(a, p, f, m, lt, np, tp, ub, L.tile, tv);
     }
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
@@ -228,23 +340,8 @@ __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, ui
     const uint32_t chunk = (np + wpp * kWave - 1) / (wpp * kWave) * kWave;
     const uint32_t c_lo = wi * chunk;
     const uint32_t c_hi = active ? (c_lo + chunk < np ? c_lo + chunk : np) : 0u;   // may be <= c_lo
-    const float qmaxf = (float)a.qmax;
     double sums[6] = {0, 0, 0, 0, 0, 0};
-    uint32_t tot = 0;
-    for (uint32_t base = c_lo; base < c_hi; base += kWave) {
-        const uint32_t s = base + lane;
-        if (s < c_hi) {
-            float w;
-            const uint32_t Q = stream_q(ub[s], lstar, qmaxf, w);
-            tot += Q;
-            const double wd = (double)w;
-            sums[0] += wd;
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-                sums[1 + c] += wd * (double)a.pout[(size_t)c * N + pe_base + s];
-            if (trace) D->t_q[pe_base + s] = Q;
-        }
-    }
+    const uint32_t tot = pass_b(a, ub, pe_base, c_lo, c_hi, lstar, sums);
     {
         const uint32_t wt = lane63(wave_incl_scan_u32(tot));
         if (lane == 0) L.wq[wave] = wt;
@@ -260,45 +357,11 @@ __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, ui
     const uint32_t V = mulshift(philox(m, a.k, f, kTagResample << 24, a.key0, a.key1).x, T);
 
     // ---- pass C (step 7): ancestors of the output ranks
-    if (!active) {
-    } else if (a.force_anc) {   // replay of another run's choices (test support)
-        for (uint32_t j = lt; j < np; j += tp) {
-            const uint32_t anc = a.force_anc[pe_base + j];
-            a.aout[pe_base + j] = (uint16_t)anc;
-            if (trace) D->t_anc[pe_base + j] = anc;
-        }
-    } else if (T == 0) {   // no weight anywhere: every rank takes slot 0, as in k_step
-        for (uint32_t j = lt; j < np; j += tp) {
-            a.aout[pe_base + j] = 0;
-            if (trace) D->t_anc[pe_base + j] = 0;
-        }
-    } else {
-        const double inv_T = 1.0 / (double)T;
-        for (uint32_t base = c_lo; base < c_hi; base += kWave) {
-            const uint32_t s = base + lane;
-            float w;
-            const uint32_t Q = (s < c_hi) ? stream_q(ub[s], lstar, qmaxf, w) : 0u;
-            const uint32_t incl = wave_incl_scan_u32(Q);
-            // first rank of this lane's slot; non-decreasing over the lanes
-            const uint32_t j0 = first_offspring(carry + incl - Q, np, T, V, inv_T);
-            carry += lane63(incl);
-            const uint32_t J0 = (uint32_t)__builtin_amdgcn_readlane((int)j0, 0);
-            const uint32_t J1 = first_offspring(carry, np, T, V, inv_T);   // wave-uniform
-            for (uint32_t r0 = J0; r0 < J1; r0 += kWave) {
-                const uint32_t r = r0 + lane;
-                // the last lane whose first rank is <= r owns rank r
-                uint32_t lo = 0;
-#pragma unroll
-                for (uint32_t step = kWave / 2; step >= 1; step /= 2) {
-                    const uint32_t cand = lo + step;
-                    if ((uint32_t)__shfl((int)j0, (int)cand) <= r) lo = cand;
-                }
-                if (r < J1) {
-                    a.aout[pe_base + r] = (uint16_t)(base + lo);
-                    if (trace) D->t_anc[pe_base + r] = base + lo;
-                }
-            }
-        }
+    if (active) {
+        if (a.force_anc || T == 0)
+            fixed_ancestors(a, pe_base, lt, np, tp);
+        else
+            pass_c(a, ub, pe_base, c_lo, c_hi, lstar, carry, T, V);
     }
 
     // ---- steps 8-9: the records of the group's PEs, all by thread 0 (the
@@ -347,6 +410,160 @@ __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, ui
                          L.wsum, a.mout + f);
             if (tid == 0) atomicExch(&a.arrive[f], 0u);
         }
+    }
+}
+
+
+// ---------------------------------------------------------------- split PEs
+// A PE beyond the LDS stage split over G workgroups of the same size, each
+// taking the S = kSplitSlots consecutive slots [g S, g S + S) of its PE
+// (workgroup w is segment g = w mod G of PE w / G).  The three passes become
+// three launches, the workgroup boundary replacing the barriers of
+// k_step_flex: (1) steps 3-5 and the segment's maximum of u; (2) Q, the FP64
+// sums and the wave totals of Q; (3) the carry of every wave from the totals
+// of the PE's earlier segments and waves, the ancestors, and the PE record
+// (segment 0).  Per-segment results go through the context's SplitBufs.
+constexpr uint32_t kSplitBlock = 512;
+constexpr uint32_t kSplitSlots = 4 * kSplitBlock;
+constexpr uint32_t kSplitWaves = kSplitBlock / 64;
+
+struct SplitBufs {
+    float *u;          // [N] log-weights
+    float *seg_max;    // [F M G] segment maxima of u
+    uint32_t *seg_wq;  // [F M G][kSplitWaves] wave totals of Q
+    double *seg_sum;   // [F M G][6] segment sums (W, W x)
+    uint32_t G;        // segments per PE
+};
+
+__host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0); }
+
+// The segment's slot range and the PE's maximum of u (from the segment maxima).
+struct Segment {
+    uint32_t pe, f, m, g, s0, s1, pe_base;
+};
+__device__ __forceinline__ Segment segment_of(const StepArgs &a, const SplitBufs &sb) {
+    Segment s;
+    s.pe = blockIdx.x / sb.G;
+    s.g = blockIdx.x - s.pe * sb.G;
+    s.f = s.pe / a.M;
+    s.m = s.pe - s.f * a.M;
+    s.s0 = s.g * kSplitSlots;
+    s.s1 = s.s0 + kSplitSlots < a.np ? s.s0 + kSplitSlots : a.np;
+    s.pe_base = s.pe * a.np;
+    return s;
+}
+__device__ __forceinline__ float pe_max_u(const SplitBufs &sb, uint32_t pe) {
+    float l = sb.seg_max[(size_t)pe * sb.G];
+    for (uint32_t g = 1; g < sb.G; ++g) l = fmaxf(l, sb.seg_max[(size_t)pe * sb.G + g]);
+    return l;
+}
+
+template <int HALF, int LIK>
+__global__ __launch_bounds__(kSplitBlock) void k_split_weights(StepArgs a, SplitBufs sb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool POINT = LIK == kLikPoint;
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const Segment sg = segment_of(a, sb);
+    FlexLds L = flex_carve(smem);
+    if (wave == 0) prologue_wave(a, sg.f, sg.m, L.pro, lane);
+    const TileView tv = load_tile<POINT>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
+    __syncthreads();   // prologue and tile visible
+    const Prologue p = uniform_prologue(L.pro);
+    float umax = pass_a<HALF, LIK>(a, p, sg.f, sg.m, sg.s0 + tid, sg.s1, kSplitBlock,
+                                   sb.u + sg.pe_base, L.tile, tv);
+    umax = wave_max_f32(umax);
+    if (lane == 0) L.wmax[wave] = umax;
+    __syncthreads();
+    if (tid == 0) {
+        float l = L.wmax[0];
+        for (uint32_t w = 1; w < kSplitWaves; ++w) l = fmaxf(l, L.wmax[w]);
+        sb.seg_max[blockIdx.x] = l;
+        if (sg.g == 0) {
+            if (sg.m == 0) {
+                a.nex_used[sg.f] = p.nex;
+                if (a.nex_rec) a.nex_rec[sg.f] = p.nex;
+            }
+            if (a.dbg && a.dbg->t_q) a.dbg->t_pred[sg.pe] = p.pred;
+        }
+    }
+}
+
+// The wave's contiguous share of the segment (64 slots at a time).
+__device__ __forceinline__ void wave_chunk(const Segment &sg, uint32_t wave, uint32_t &c_lo,
+                                           uint32_t &c_hi) {
+    const uint32_t len = sg.s1 - sg.s0;
+    const uint32_t chunk = (len + kSplitWaves * kWave - 1) / (kSplitWaves * kWave) * kWave;
+    c_lo = sg.s0 + wave * chunk;
+    c_hi = c_lo + chunk < sg.s1 ? c_lo + chunk : sg.s1;
+}
+
+__global__ __launch_bounds__(kSplitBlock) void k_split_totals(StepArgs a, SplitBufs sb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const Segment sg = segment_of(a, sb);
+    FlexLds L = flex_carve(smem);
+    const float lstar = pe_max_u(sb, sg.pe);
+    uint32_t c_lo, c_hi;
+    wave_chunk(sg, wave, c_lo, c_hi);
+    double sums[6] = {0, 0, 0, 0, 0, 0};
+    const uint32_t tot = pass_b(a, sb.u + sg.pe_base, sg.pe_base, c_lo, c_hi, lstar, sums);
+    const uint32_t wt = lane63(wave_incl_scan_u32(tot));
+    if (lane == 0) sb.seg_wq[(size_t)blockIdx.x * kSplitWaves + wave] = wt;
+    const double s6 = wave_total6_f64(sums, lane);
+    if ((lane & 7u) == 0 && lane < 48) L.wsum[wave * 6 + (lane >> 3)] = s6;
+    __syncthreads();
+    if (tid < 6) {
+        double acc = 0;
+        for (uint32_t w = 0; w < kSplitWaves; ++w) acc += L.wsum[w * 6 + tid];
+        sb.seg_sum[(size_t)blockIdx.x * 6 + tid] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, SplitBufs sb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const Segment sg = segment_of(a, sb);
+    FlexLds L = flex_carve(smem);
+    const float lstar = pe_max_u(sb, sg.pe);
+    // wave 0: the sum of the wave totals of the PE's earlier segments and of
+    // this segment's earlier waves (exclusive prefix in (segment, wave)
+    // order), and the total T
+    if (wave == 0) {
+        const uint32_t *wq = sb.seg_wq + (size_t)sg.pe * sb.G * kSplitWaves;
+        const uint32_t n = sb.G * kSplitWaves, mine = sg.g * kSplitWaves;
+        uint32_t run = 0;
+        for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+            const uint32_t i = i0 + lane;
+            const uint32_t v = i < n ? wq[i] : 0u;
+            const uint32_t incl = wave_incl_scan_u32(v);
+            if (i >= mine && i < mine + kSplitWaves) L.wq[i - mine] = run + incl - v;
+            run += lane63(incl);
+        }
+        if (lane == 0) *L.flag = run;
+    }
+    __syncthreads();
+    const uint32_t T = *L.flag, carry = L.wq[wave];
+    const uint32_t V =
+        mulshift(philox(sg.m, a.k, sg.f, kTagResample << 24, a.key0, a.key1).x, T);
+    if (a.force_anc || T == 0) {
+        fixed_ancestors(a, sg.pe_base, sg.s0 + tid, sg.s1, kSplitBlock);
+    } else {
+        uint32_t c_lo, c_hi;
+        wave_chunk(sg, wave, c_lo, c_hi);
+        pass_c(a, sb.u + sg.pe_base, sg.pe_base, c_lo, c_hi, lstar, carry, T, V);
+    }
+    // steps 8-9: the PE record, from the segment sums in segment order
+    if (sg.g == 0 && tid == 0) {
+        double t6[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t g = 0; g < sb.G; ++g)
+            for (int c = 0; c < 6; ++c) t6[c] += sb.seg_sum[((size_t)sg.pe * sb.G + g) * 6 + c];
+        pf_pe_record rec;
+        rec.log_mass = (lstar == -INFINITY) ? -INFINITY : (double)lstar + log(t6[0]);
+        for (int c = 0; c < 5; ++c) rec.xhat[c] = t6[1 + c] / t6[0];
+        rec.lstar = lstar;
+        rec.total_q = T;
+        a.rout[sg.pe] = rec;
+        if (a.dbg && a.dbg->t_q) a.dbg->t_v[sg.pe] = V;
     }
 }
 

@@ -209,6 +209,7 @@ static int traj_main() {
         {1, 4, 256, 128, 128, 0, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 1},
         {1, 300, 64, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},    // more than 256 PEs
         {3, 5, 77, 128, 128, 1, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 6},
+        {1, 2, 5000, 96, 96, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 8},     // split PEs
     };
     std::mt19937_64 rng(7);
     for (const Case &cs : cases) {
@@ -295,7 +296,8 @@ static std::vector<uint32_t> systematic(const uint32_t *q, uint32_t n, uint32_t 
 }
 
 // Iterations of context b (ppw = 0: through the library; else k_step_flex
-// launched directly) against context a (k_step), both from the same state
+// launched directly) against context a (through the library: k_step, or for
+// PEs beyond the LDS stage the split kernels), both from the same state
 // before every iteration: every traced value and the stored particles equal,
 // the records within FP64 summation order.
 static int compare_with_k_step(const Case &cs, uint32_t ppw_cfg, uint32_t block_cfg,
@@ -396,7 +398,16 @@ static int stream_main() {
         {{2, 7, 130, 96, 80, 1, 0, 9, 0, 4, 0.1f, 5.f, 2.f, 28}, 5, 640},   // grouped ring
     };
     for (const Grouped &g : grouped) bad += compare_with_k_step(g.cs, g.ppw, g.block, 0, true, rng);
-    // (3) contexts beyond the LDS stage, through the library
+    // (3) contexts beyond the LDS stage: the library's split PEs (three
+    // launches) against one streamed PE per workgroup, then through pf_step
+    // against systematic resampling of the traced weights
+    const Case big_cmp[] = {
+        {1, 2, 5000, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 31},
+        {2, 3, 8192, 96, 96, 0, 2, 9, 0, 0, 0.5f, 10.f, 2.f, 32},
+        {1, 3, 4097, 64, 64, 1, 1, 9, 0, 0, 0.1f, 5.f, 1.f, 33},
+        {1, 2, 20000, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 34},
+    };
+    for (const Case &cs : big_cmp) bad += compare_with_k_step(cs, 0, 0, 1, false, rng);
     const Case big[] = {
         {1, 2, 5000, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},
         {2, 3, 8192, 96, 96, 0, 2, 9, 1024, 0, 0.5f, 10.f, 2.f, 12},
