@@ -32,6 +32,11 @@ CASES = {
                          lik_mode=1, noise_sigma=1.0, seed=43),
     "persistent_1x4x256": dict(BASE, n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128,
                                mode=1, lik_mode=0, launch=2, seed=44),
+    # several PEs per workgroup; PEs split over workgroups (rows from k_global)
+    "grouped_2x8x200": dict(BASE, n_filters=2, n_pe=8, n_per_pe=200, width=128, height=128,
+                            mode=1, lik_mode=0, pes_per_wg=4, seed=45),
+    "split_1x4x9000": dict(BASE, n_filters=1, n_pe=4, n_per_pe=9000, width=128, height=128,
+                           mode=1, lik_mode=0, seed=46),
 }
 KEYS = ("x_global", "log_mass_glob", "pe_eff", "n_ex", "n_ex_next", "log_z_inc")
 
