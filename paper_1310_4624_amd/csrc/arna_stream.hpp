@@ -452,11 +452,13 @@ __device__ __forceinline__ Segment segment_of(const StepArgs &a, const SplitBufs
     s.pe_base = s.pe * a.np;
     return s;
 }
+// (every lane loads at most one segment maximum: G <= 32 = 65536 / 2048)
 __device__ __forceinline__ float pe_max_u(const SplitBufs &sb, uint32_t pe) {
-    float l = sb.seg_max[(size_t)pe * sb.G];
-    for (uint32_t g = 1; g < sb.G; ++g) l = fmaxf(l, sb.seg_max[(size_t)pe * sb.G + g]);
-    return l;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const float l = lane < sb.G ? sb.seg_max[(size_t)pe * sb.G + lane] : -INFINITY;
+    return wave_max_f32(l);
 }
+constexpr uint32_t kMaxSegments = PF_MAX_PER_PE / kSplitSlots;   // 32
 
 template <int HALF, int LIK>
 __global__ __launch_bounds__(kSplitBlock) void k_split_weights(StepArgs a, SplitBufs sb) {
@@ -529,14 +531,21 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, Spl
     // this segment's earlier waves (exclusive prefix in (segment, wave)
     // order), and the total T
     if (wave == 0) {
+        constexpr uint32_t kPer = kMaxSegments * kSplitWaves / kWave;   // values per lane
         const uint32_t *wq = sb.seg_wq + (size_t)sg.pe * sb.G * kSplitWaves;
         const uint32_t n = sb.G * kSplitWaves, mine = sg.g * kSplitWaves;
+        uint32_t v[kPer];
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {   // all loads in flight before the scans
+            const uint32_t i = j * kWave + lane;
+            v[j] = i < n ? wq[i] : 0u;
+        }
         uint32_t run = 0;
-        for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
-            const uint32_t i = i0 + lane;
-            const uint32_t v = i < n ? wq[i] : 0u;
-            const uint32_t incl = wave_incl_scan_u32(v);
-            if (i >= mine && i < mine + kSplitWaves) L.wq[i - mine] = run + incl - v;
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint32_t i = j * kWave + lane;
+            const uint32_t incl = wave_incl_scan_u32(v[j]);
+            if (i >= mine && i < mine + kSplitWaves) L.wq[i - mine] = run + incl - v[j];
             run += lane63(incl);
         }
         if (lane == 0) *L.flag = run;
@@ -552,11 +561,20 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, Spl
         wave_chunk(sg, wave, c_lo, c_hi);
         pass_c(a, sb.u + sg.pe_base, sg.pe_base, c_lo, c_hi, lstar, carry, T, V);
     }
-    // steps 8-9: the PE record, from the segment sums in segment order
-    if (sg.g == 0 && tid == 0) {
+    // steps 8-9: the PE record from the segment sums (lane g loads segment
+    // g's, the wave totals them)
+    if (sg.g == 0 && wave == 0) {
         double t6[6] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t g = 0; g < sb.G; ++g)
-            for (int c = 0; c < 6; ++c) t6[c] += sb.seg_sum[((size_t)sg.pe * sb.G + g) * 6 + c];
+        if (lane < sb.G)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) t6[c] = sb.seg_sum[((size_t)sg.pe * sb.G + lane) * 6 + c];
+        const double tw = wave_total6_f64(t6, lane);
+        if ((lane & 7u) == 0 && lane < 48) L.wsum[lane >> 3] = tw;
+    }
+    __syncthreads();
+    if (sg.g == 0 && tid == 0) {
+        double t6[6];
+        for (int c = 0; c < 6; ++c) t6[c] = L.wsum[c];
         pf_pe_record rec;
         rec.log_mass = (lstar == -INFINITY) ? -INFINITY : (double)lstar + log(t6[0]);
         for (int c = 0; c < 5; ++c) rec.xhat[c] = t6[1 + c] / t6[0];

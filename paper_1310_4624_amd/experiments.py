@@ -266,6 +266,9 @@ def main():
     ap.add_argument("--n-per-pe", type=int, default=4096)
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--curves", action="store_true", help="include the per-step curves")
+    ap.add_argument("--shapes", default="",
+                    help="scaling: only these PE counts and launch shapes, as n_pe:BxP,... "
+                         "(B = block_size, P = pes_per_wg; 0x0 = the defaults)")
     ap.add_argument("--tuned", action="store_true",
                     help="scaling: also the autotuner's launch shape (workgroup size, PEs per "
                          "workgroup)")
@@ -311,6 +314,14 @@ def main():
                     print(json.dumps(r), flush=True)
         return
     if args.what == "scaling":
+        if args.shapes:   # "n_pe:BxP,...": given launch shapes only
+            for item in args.shapes.split(","):
+                n_pe, shape = item.split(":")
+                bs, ppw = shape.split("x")
+                for mode in args.modes.split(","):
+                    print(json.dumps(scaling(mode, int(n_pe), block_size=int(bs),
+                                             pes_per_wg=int(ppw))), flush=True)
+            return
         for n_pe in (256, 512, 1024, 2048, 4096, 8192):
             for mode in args.modes.split(","):
                 print(json.dumps(scaling(mode, n_pe)), flush=True)
