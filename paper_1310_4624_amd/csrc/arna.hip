@@ -130,6 +130,14 @@ struct pf_batch {
         std::vector<uint32_t> members;   // context indices
         std::vector<uint32_t> first;     // first workgroup of each member, then the total
         uint32_t *d_first;
+        // kind 0: k_step_batch; 1: k_step_flex_batch (ppw PEs per workgroup,
+        // log-weight arrays d_u per member); 2: the three split launches
+        // (fn, then k_split_totals_batch and k_split_ancestors_batch; buffers
+        // d_sb per member)
+        int kind;
+        uint32_t ppw;
+        float **d_u;
+        SplitBufs *d_sb;
     };
     std::vector<pf_ctx *> ctx;
     std::vector<Group> groups;
@@ -345,6 +353,37 @@ template <int HALF, int LIK>
 void *batch_kernel_ppt(uint32_t ppt) {
     return ppt == 1 ? batch_kernel<1, HALF, LIK>()
                     : (ppt == 2 ? batch_kernel<2, HALF, LIK>() : batch_kernel<4, HALF, LIK>());
+}
+
+template <int HALF, int LIK, bool ULDS>
+void *flex_batch_kernel() {
+    return reinterpret_cast<void *>(&k_step_flex_batch<HALF, LIK, ULDS>);
+}
+template <int HALF, int LIK>
+void *split_batch_kernel() {
+    return reinterpret_cast<void *>(&k_split_weights_batch<HALF, LIK>);
+}
+void *split_totals_batch_kernel() { return reinterpret_cast<void *>(&k_split_totals_batch); }
+void *split_ancestors_batch_kernel() {
+    return reinterpret_cast<void *>(&k_split_ancestors_batch);
+}
+
+// Batched variants of k_step_flex and of the split kernels, for the 9 x 9
+// patch and point observations (others run one by one).
+void *pick_flex_batch_kernel(uint32_t half, uint32_t lik_mode, bool ulds) {
+    if (lik_mode == PF_LIK_POINT)
+        return ulds ? flex_batch_kernel<0, kLikPoint, true>() : flex_batch_kernel<0, kLikPoint, false>();
+    if (half != 4) return nullptr;
+    if (lik_mode == PF_LIK_POISSON)
+        return ulds ? flex_batch_kernel<4, kLikPoisson, true>()
+                    : flex_batch_kernel<4, kLikPoisson, false>();
+    return ulds ? flex_batch_kernel<4, kLikGauss, true>() : flex_batch_kernel<4, kLikGauss, false>();
+}
+void *pick_split_batch_kernel(uint32_t half, uint32_t lik_mode) {
+    if (lik_mode == PF_LIK_POINT) return split_batch_kernel<0, kLikPoint>();
+    if (half != 4) return nullptr;
+    if (lik_mode == PF_LIK_POISSON) return split_batch_kernel<4, kLikPoisson>();
+    return split_batch_kernel<4, kLikGauss>();
 }
 
 void *pick_batch_kernel(uint32_t ppt, uint32_t half, uint32_t lik_mode) {
@@ -1213,27 +1252,35 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
     b->args_cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
         pf_ctx *c = ctxs[i];
-        void *fn = c->flex ? nullptr : pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
+        const int kind = c->split ? 2 : (c->flex ? 1 : 0);
+        void *fn = kind == 2 ? pick_split_batch_kernel(c->half, c->cfg.lik_mode)
+                   : kind == 1 ? pick_flex_batch_kernel(c->half, c->cfg.lik_mode, !c->streamk)
+                               : pick_batch_kernel(c->ppt, c->half, c->cfg.lik_mode);
         if (!fn || c->FM > 0xFFFFFFFFull) {
             b->solo.push_back(i);
             continue;
         }
+        const uint32_t block = kind == 2 ? kSplitBlock : c->block;
         pf_batch::Group *g = nullptr;
         for (auto &h : b->groups)
-            if (h.fn == fn && h.block == c->block) g = &h;
+            if (h.fn == fn && h.block == block && h.ppw == c->ppw) g = &h;
         if (!g) {
-            b->groups.push_back(pf_batch::Group{fn, c->ppt, c->block, 0, 0, {}, {}, nullptr});
+            pf_batch::Group ng{fn, c->ppt, block, 0, 0, {}, {}, nullptr, kind, c->ppw, nullptr,
+                               nullptr};
+            b->groups.push_back(ng);
             g = &b->groups.back();
         }
         g->members.push_back(i);
-        if (c->lds > g->lds) g->lds = c->lds;
+        const size_t lds = kind == 2 ? split_lds_bytes() : c->lds;
+        if (lds > g->lds) g->lds = lds;
     }
     int rc = PF_OK;
     for (auto &g : b->groups) {
         uint64_t acc = 0;
         for (uint32_t i : g.members) {
+            const pf_ctx *c = b->ctx[i];
             g.first.push_back((uint32_t)acc);
-            acc += b->ctx[i]->FM;
+            acc += g.kind == 2 ? c->FM * c->sb.G : (g.kind == 1 ? c->n_wg : c->FM);
         }
         if (acc > 0x7FFFFFFFull) rc = PF_EUNSUPPORTED;
         g.blocks = (uint32_t)acc;
@@ -1247,6 +1294,23 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
         if (rc == PF_OK && hipFuncSetAttribute(g.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)g.lds) != hipSuccess)
             rc = PF_EHIP;
+        // the members' log-weight arrays or split buffers
+        if (rc == PF_OK && g.kind == 1) {
+            std::vector<float *> u;
+            for (uint32_t i : g.members) u.push_back(b->ctx[i]->u);
+            rc = dev_alloc(&g.d_u, u.size());
+            if (rc == PF_OK && hipMemcpy(g.d_u, u.data(), u.size() * sizeof(float *),
+                                         hipMemcpyHostToDevice) != hipSuccess)
+                rc = PF_EHIP;
+        }
+        if (rc == PF_OK && g.kind == 2) {
+            std::vector<SplitBufs> sb;
+            for (uint32_t i : g.members) sb.push_back(b->ctx[i]->sb);
+            rc = dev_alloc(&g.d_sb, sb.size());
+            if (rc == PF_OK && hipMemcpy(g.d_sb, sb.data(), sb.size() * sizeof(SplitBufs),
+                                         hipMemcpyHostToDevice) != hipSuccess)
+                rc = PF_EHIP;
+        }
     }
     b->ev_fork = nullptr;
     const size_t lanes = b->groups.size() + b->solo.size();
@@ -1278,6 +1342,30 @@ int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out) {
 }  // extern "C"
 
 namespace {
+
+// One iteration of a batch group: its members' arguments start at ga.
+hipError_t launch_group(const pf_batch::Group &g, const StepArgs *ga, hipStream_t st) {
+    uint32_t cnt = (uint32_t)g.members.size();
+    const uint32_t *first = g.d_first;
+    if (g.kind == 0) {
+        void *kargs[] = {&ga, &first, &cnt};
+        return hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds, st);
+    }
+    if (g.kind == 1) {
+        float *const *u = g.d_u;
+        uint32_t ppw = g.ppw;
+        void *kargs[] = {&ga, &first, &cnt, &u, &ppw};
+        return hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds, st);
+    }
+    const SplitBufs *sb = g.d_sb;
+    void *kargs[] = {&ga, &first, &cnt, &sb};
+    void *fns[] = {g.fn, split_totals_batch_kernel(), split_ancestors_batch_kernel()};
+    for (void *fn : fns) {
+        const hipError_t e = hipLaunchKernel(fn, dim3(g.blocks), dim3(g.block), kargs, g.lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 // Graph mode of pf_batch_run, in runs of at most kRingSteps iterations.  The
 // ring tables are rebuilt before a run when they do not cover it (outside the
@@ -1351,14 +1439,11 @@ int batch_run_graph(pf_batch *b, const float *const *d_frames, const uint64_t *f
                 for (size_t gi = 0; gi < b->groups.size(); ++gi) {
                     auto &g = b->groups[gi];
                     const StepArgs *ga = b->d_args + (size_t)t * nb + slot;
-                    uint32_t cnt = (uint32_t)g.members.size();
-                    void *kargs[] = {&ga, &g.d_first, &cnt};
-                    if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds,
-                                        b->workers[gi % nw]) != hipSuccess) {
+                    if (launch_group(g, ga, b->workers[gi % nw]) != hipSuccess) {
                         rc = PF_EHIP;
                         break;
                     }
-                    slot += cnt;
+                    slot += (uint32_t)g.members.size();
                 }
             }
             for (size_t w = 0; w < nw; ++w)
@@ -1516,11 +1601,8 @@ int batch_run(pf_batch *b, const float *const *d_frames, const uint64_t *frame_s
             if (rc != PF_OK) break;
             auto &g = b->groups[gi];
             const StepArgs *ga = d_args + (size_t)t * nb + slot;
-            uint32_t cnt = (uint32_t)g.members.size();
-            void *kargs[] = {&ga, &g.d_first, &cnt};
-            if (hipLaunchKernel(g.fn, dim3(g.blocks), dim3(g.block), kargs, g.lds,
-                                b->workers[gi % nw]) != hipSuccess)
-                rc = PF_EHIP;
+            const uint32_t cnt = (uint32_t)g.members.size();
+            if (launch_group(g, ga, b->workers[gi % nw]) != hipSuccess) rc = PF_EHIP;
             for (uint32_t i : g.members) {
                 pf_ctx *c = b->ctx[i];
                 const uint64_t k = c->step + 1;
@@ -1587,8 +1669,11 @@ void pf_batch_destroy(pf_batch *b) {
     }
     for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    for (auto &g : b->groups)
+    for (auto &g : b->groups) {
         if (g.d_first) (void)hipFree(g.d_first);
+        if (g.d_u) (void)hipFree(g.d_u);
+        if (g.d_sb) (void)hipFree(g.d_sb);
+    }
     for (auto &e : b->graphs) (void)hipGraphExecDestroy(e.second);
     if (b->d_args) (void)hipFree(b->d_args);
     delete b;

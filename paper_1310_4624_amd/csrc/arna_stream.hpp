@@ -291,14 +291,15 @@ __device__ __forceinline__ void fixed_ancestors(const StepArgs &a, uint32_t pe_b
 // in LDS (ppw N_p floats); else they go to u_hbm [N] (context scratch, fully
 // rewritten).
 template <int HALF, int LIK, bool ULDS>
-__global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw) {
+__device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const uint32_t ppw,
+                                          const uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x;
     const uint32_t M = a.M, np = a.np;
     const uint32_t B = blockDim.x, tp = B / ppw;
     const uint32_t G = (M + ppw - 1) / ppw;   // workgroups per filter
-    const uint32_t f = blockIdx.x / G, m0 = (blockIdx.x % G) * ppw;
+    const uint32_t f = bid / G, m0 = (bid % G) * ppw;
     const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
     // this thread's PE in the group (whole waves per PE: the same in every
     // lane), its rank in the PE's thread group
@@ -414,6 +415,38 @@ __global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, ui
 }
 
 
+template <int HALF, int LIK, bool ULDS>
+__global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw) {
+    flex_body<HALF, LIK, ULDS>(a, u_hbm, ppw, blockIdx.x);
+}
+
+// The context of workgroup `bid` in a batched launch: contexts own the
+// workgroup ranges [first[i], first[i + 1]).
+__device__ __forceinline__ uint32_t batch_context(const uint32_t *first, uint32_t n,
+                                                  uint32_t bid) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (first[mid] <= bid)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Several contexts with several PEs per workgroup (or streamed PEs) in one
+// launch: context i has arguments args[i], log-weight array u[i] and the
+// workgroups [first[i], first[i + 1]); all share ppw and the block size.
+template <int HALF, int LIK, bool ULDS>
+__global__ __launch_bounds__(1024) void k_step_flex_batch(const StepArgs *args,
+                                                          const uint32_t *first, uint32_t n,
+                                                          float *const *u, uint32_t ppw) {
+    const uint32_t i = batch_context(first, n, blockIdx.x);
+    const StepArgs a = args[i];
+    flex_body<HALF, LIK, ULDS>(a, u[i], ppw, blockIdx.x - first[i]);
+}
+
 // ---------------------------------------------------------------- split PEs
 // A PE beyond the LDS stage split over G workgroups of the same size, each
 // taking the S = kSplitSlots consecutive slots [g S, g S + S) of its PE
@@ -439,12 +472,14 @@ __host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0
 
 // The segment's slot range and the PE's maximum of u (from the segment maxima).
 struct Segment {
-    uint32_t pe, f, m, g, s0, s1, pe_base;
+    uint32_t bid, pe, f, m, g, s0, s1, pe_base;   // bid: the segment's workgroup in its context
 };
-__device__ __forceinline__ Segment segment_of(const StepArgs &a, const SplitBufs &sb) {
+__device__ __forceinline__ Segment segment_of(const StepArgs &a, const SplitBufs &sb,
+                                              const uint32_t bid) {
     Segment s;
-    s.pe = blockIdx.x / sb.G;
-    s.g = blockIdx.x - s.pe * sb.G;
+    s.bid = bid;
+    s.pe = bid / sb.G;
+    s.g = bid - s.pe * sb.G;
     s.f = s.pe / a.M;
     s.m = s.pe - s.f * a.M;
     s.s0 = s.g * kSplitSlots;
@@ -461,11 +496,12 @@ __device__ __forceinline__ float pe_max_u(const SplitBufs &sb, uint32_t pe) {
 constexpr uint32_t kMaxSegments = PF_MAX_PER_PE / kSplitSlots;   // 32
 
 template <int HALF, int LIK>
-__global__ __launch_bounds__(kSplitBlock) void k_split_weights(StepArgs a, SplitBufs sb) {
+__device__ __forceinline__ void split_weights_body(const StepArgs &a, const SplitBufs &sb,
+                                                   const uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const Segment sg = segment_of(a, sb);
+    const Segment sg = segment_of(a, sb, bid);
     FlexLds L = flex_carve(smem);
     if (wave == 0) prologue_wave(a, sg.f, sg.m, L.pro, lane);
     const TileView tv = load_tile<POINT>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
@@ -479,7 +515,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_weights(StepArgs a, Split
     if (tid == 0) {
         float l = L.wmax[0];
         for (uint32_t w = 1; w < kSplitWaves; ++w) l = fmaxf(l, L.wmax[w]);
-        sb.seg_max[blockIdx.x] = l;
+        sb.seg_max[sg.bid] = l;
         if (sg.g == 0) {
             if (sg.m == 0) {
                 a.nex_used[sg.f] = p.nex;
@@ -499,10 +535,11 @@ __device__ __forceinline__ void wave_chunk(const Segment &sg, uint32_t wave, uin
     c_hi = c_lo + chunk < sg.s1 ? c_lo + chunk : sg.s1;
 }
 
-__global__ __launch_bounds__(kSplitBlock) void k_split_totals(StepArgs a, SplitBufs sb) {
+__device__ __forceinline__ void split_totals_body(const StepArgs &a, const SplitBufs &sb,
+                                                  const uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const Segment sg = segment_of(a, sb);
+    const Segment sg = segment_of(a, sb, bid);
     FlexLds L = flex_carve(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     uint32_t c_lo, c_hi;
@@ -510,21 +547,22 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_totals(StepArgs a, SplitB
     double sums[6] = {0, 0, 0, 0, 0, 0};
     const uint32_t tot = pass_b(a, sb.u + sg.pe_base, sg.pe_base, c_lo, c_hi, lstar, sums);
     const uint32_t wt = lane63(wave_incl_scan_u32(tot));
-    if (lane == 0) sb.seg_wq[(size_t)blockIdx.x * kSplitWaves + wave] = wt;
+    if (lane == 0) sb.seg_wq[(size_t)sg.bid * kSplitWaves + wave] = wt;
     const double s6 = wave_total6_f64(sums, lane);
     if ((lane & 7u) == 0 && lane < 48) L.wsum[wave * 6 + (lane >> 3)] = s6;
     __syncthreads();
     if (tid < 6) {
         double acc = 0;
         for (uint32_t w = 0; w < kSplitWaves; ++w) acc += L.wsum[w * 6 + tid];
-        sb.seg_sum[(size_t)blockIdx.x * 6 + tid] = acc;
+        sb.seg_sum[(size_t)sg.bid * 6 + tid] = acc;
     }
 }
 
-__global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, SplitBufs sb) {
+__device__ __forceinline__ void split_ancestors_body(const StepArgs &a, const SplitBufs &sb,
+                                                     const uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const Segment sg = segment_of(a, sb);
+    const Segment sg = segment_of(a, sb, bid);
     FlexLds L = flex_carve(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     // wave 0: the sum of the wave totals of the PE's earlier segments and of
@@ -583,6 +621,49 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, Spl
         a.rout[sg.pe] = rec;
         if (a.dbg && a.dbg->t_q) a.dbg->t_v[sg.pe] = V;
     }
+}
+
+
+// The three launches of a split iteration, for one context and batched (the
+// contexts of a batched launch own the workgroup ranges [first[i],
+// first[i + 1]) and have the buffers sb[i]).
+template <int HALF, int LIK>
+__global__ __launch_bounds__(kSplitBlock) void k_split_weights(StepArgs a, SplitBufs sb) {
+    split_weights_body<HALF, LIK>(a, sb, blockIdx.x);
+}
+__global__ __launch_bounds__(kSplitBlock) void k_split_totals(StepArgs a, SplitBufs sb) {
+    split_totals_body(a, sb, blockIdx.x);
+}
+__global__ __launch_bounds__(kSplitBlock) void k_split_ancestors(StepArgs a, SplitBufs sb) {
+    split_ancestors_body(a, sb, blockIdx.x);
+}
+template <int HALF, int LIK>
+__global__ __launch_bounds__(kSplitBlock) void k_split_weights_batch(const StepArgs *args,
+                                                                     const uint32_t *first,
+                                                                     uint32_t n,
+                                                                     const SplitBufs *sb) {
+    const uint32_t i = batch_context(first, n, blockIdx.x);
+    const StepArgs a = args[i];
+    const SplitBufs s = sb[i];
+    split_weights_body<HALF, LIK>(a, s, blockIdx.x - first[i]);
+}
+__global__ __launch_bounds__(kSplitBlock) void k_split_totals_batch(const StepArgs *args,
+                                                                    const uint32_t *first,
+                                                                    uint32_t n,
+                                                                    const SplitBufs *sb) {
+    const uint32_t i = batch_context(first, n, blockIdx.x);
+    const StepArgs a = args[i];
+    const SplitBufs s = sb[i];
+    split_totals_body(a, s, blockIdx.x - first[i]);
+}
+__global__ __launch_bounds__(kSplitBlock) void k_split_ancestors_batch(const StepArgs *args,
+                                                                       const uint32_t *first,
+                                                                       uint32_t n,
+                                                                       const SplitBufs *sb) {
+    const uint32_t i = batch_context(first, n, blockIdx.x);
+    const StepArgs a = args[i];
+    const SplitBufs s = sb[i];
+    split_ancestors_body(a, s, blockIdx.x - first[i]);
 }
 
 }  // namespace

@@ -28,6 +28,7 @@ struct Case {
     uint32_t F, M, np, W, H, mode, lik, patch, block, groups;
     float fixed, bg, noise;
     uint64_t seed;
+    uint32_t ppw = 0;   // PEs per workgroup
 };
 
 static pf_config make_cfg(const Case &c) {
@@ -39,6 +40,7 @@ static pf_config make_cfg(const Case &c) {
     p.fixed_ratio = c.fixed; p.initial_ratio = 0.1f; p.eff_cutoff = 0.99f; p.psf_sigma = 1.5f;
     p.background = c.bg; p.noise_sigma = c.noise; p.q = 0.5f; p.sigma_I = 0.5f;
     p.debug = 0; p.ring_groups = c.groups; p.block_size = c.block; p.launch = 0; p.seed = c.seed;
+    p.pes_per_wg = c.ppw;
     p.stream = nullptr;
     return p;
 }
@@ -123,10 +125,17 @@ static int batch_main(int K, int graph) {
         {1, 3, 200, 64, 64, 1, 0, 7, 0, 0, 0.1f, 5.f, 2.f, 7},
         {1, 5, 1000, 96, 80, 1, 0, 9, 512, 0, 0.1f, 5.f, 2.f, 8},
         {2, 8, 100, 96, 80, 1, 0, 9, 0, 4, 0.1f, 5.f, 2.f, 9},
+        // several PEs per workgroup (batched k_step_flex), split PEs (batched
+        // split launches)
+        {1, 4, 256, 128, 128, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 10, 2},
+        {2, 3, 130, 96, 80, 0, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 11, 3},
+        {1, 2, 5000, 96, 96, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 12},
+        {1, 2, 4500, 64, 64, 1, 2, 9, 0, 0, 0.1f, 10.f, 2.f, 13},
     };
-    if (getenv("EMU_CASES")) {   // comma-free digit list, e.g. "0134"
+    if (getenv("EMU_CASES")) {   // case indices as digits and letters (a = 10), e.g. "013b"
         std::vector<Case> sel;
-        for (const char *p = getenv("EMU_CASES"); *p; ++p) sel.push_back(cases[*p - '0']);
+        for (const char *p = getenv("EMU_CASES"); *p; ++p)
+            sel.push_back(cases[*p >= 'a' ? *p - 'a' + 10 : *p - '0']);
         cases = sel;
     }
     std::mt19937_64 rng(2024);

@@ -35,6 +35,15 @@ def _cases():
              block_size=512, seed=8),                            # 2 slots per thread
         dict(base, n_filters=2, n_pe=8, n_per_pe=100, width=96, height=80, mode=1, lik_mode=0,
              ring_groups=4, seed=9),
+        # several PEs per workgroup, and PEs beyond LDS split over workgroups
+        dict(base, n_filters=1, n_pe=4, n_per_pe=256, width=128, height=128, mode=1, lik_mode=0,
+             pes_per_wg=2, seed=10),
+        dict(base, n_filters=2, n_pe=3, n_per_pe=130, width=96, height=80, mode=0, lik_mode=1,
+             fixed_ratio=0.5, noise_sigma=1.0, pes_per_wg=3, seed=11),
+        dict(base, n_filters=1, n_pe=2, n_per_pe=5000, width=96, height=96, mode=1, lik_mode=0,
+             seed=12),
+        dict(base, n_filters=1, n_pe=2, n_per_pe=4500, width=64, height=64, mode=1, lik_mode=2,
+             background=10.0, seed=13),
     ]
 
 
