@@ -340,6 +340,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (counters or {}).get("bytes_per_launch"),
+                     "l2_hit_rate": (counters or {}).get("l2_hit_rate"),
                      "kernel": "k_step", "kernel_ms": h["kernel_ms"],
                      "bytes_per_launch": h["bytes_launch"], "kernel_sha": kernel_sha(),
                      "timed_region_ms_per_step": ms},
