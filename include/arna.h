@@ -63,12 +63,13 @@ enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the
 #define PF_MAX_PE 8192u
 #define PF_MAX_PER_PE 65536u
 /* Up to this many particles per PE a PE's particles live in LDS for the whole
- * iteration.  Larger PEs stream them through HBM (a second step kernel with the
- * same results up to the summation order of the FP64 PE sums): such contexts
- * take no block_size other than 0 or 1024, no pes_per_wg above 1 (PF_EINVAL),
- * no PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no
- * gradient recording (PF_EUNSUPPORTED), run in a batch one by one, and hold N
- * more floats of device memory (the log-weights of the iteration). */
+ * iteration.  Larger PEs stream them through HBM (other step kernels with the
+ * same results up to the summation order of the FP64 PE sums; with fewer than
+ * 256 PEs each PE is split over several workgroups): such contexts take no
+ * block_size other than 0 or 1024, no pes_per_wg above 1 (PF_EINVAL), no
+ * PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no
+ * gradient recording (PF_EUNSUPPORTED), and hold N more floats of device
+ * memory (the log-weights of the iteration). */
 #define PF_MAX_PER_PE_LDS 4096u
 #define PF_MAX_PATCH 15u
 #define PF_MAX_PARTICLES (1u << 29)   /* F M N_p: state indices are 32-bit (5 F M N_p < 2^32) */
@@ -138,9 +139,8 @@ typedef struct {
                                  * workgroup count, which pays for small N_p.  Same
                                  * results as one PE per workgroup up to the summation
                                  * order of the FP64 PE sums.  N_p <= PF_MAX_PER_PE_LDS;
-                                 * no PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, no
-                                 * gradient recording (PF_EUNSUPPORTED); a batch runs such
-                                 * contexts one by one.  The autotuner's second axis. */
+                                 * no PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT
+                                 * (PF_EUNSUPPORTED).  The autotuner's second axis. */
     uint64_t seed;              /* Philox key */
     void *stream;               /* hipStream_t or NULL */
 } pf_config;

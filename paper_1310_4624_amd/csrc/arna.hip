@@ -77,6 +77,8 @@ struct pf_ctx {
     // iteration; the per-segment results live in sb)
     bool split;
     SplitBufs sb;
+    // launch shape of the adjoint (one PE per workgroup, as k_step's default)
+    uint32_t adj_ppt, adj_block;
     float *prop[2];
     uint16_t *anc[2];
     pf_pe_record *rec[2];
@@ -829,6 +831,8 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
         c->ppt = np > 1024 ? 4 : 1;
     }
     c->half = cfg->lik_mode != PF_LIK_POINT ? cfg->patch / 2 : 0;
+    c->adj_ppt = c->flex ? (np > 1024 ? 4 : 1) : c->ppt;
+    c->adj_block = c->flex ? block_of(np) : c->block;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
     c->lds = c->streamk ? flex_lds_bytes(0)
@@ -1080,7 +1084,7 @@ void pf_destroy(pf_ctx *c) {
 
 int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
     if (!c || max_steps == 0) return PF_EINVAL;
-    if (c->cfg.lik_mode != PF_LIK_PATCH || c->flex) return PF_EUNSUPPORTED;
+    if (c->cfg.lik_mode != PF_LIK_PATCH || c->streamk) return PF_EUNSUPPORTED;
     if (!(c->cfg.q > 0.f)) return PF_EINVAL;
     if (c->g_cap || c->exchanged) return PF_ESTATE;
     const uint64_t N = c->N, FM = c->FM;
@@ -1110,7 +1114,7 @@ int pf_grad_begin(pf_ctx *c, uint32_t max_steps) {
     }
     if (rc == PF_OK && !c->g_theta) rc = dev_alloc(&c->g_theta, 3 * FM);
     if (rc == PF_OK) {
-        void *fn = pick_adjoint_kernel(c->ppt, c->half);
+        void *fn = pick_adjoint_kernel(c->adj_ppt, c->half);
         if (!fn || hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)adjoint_lds_bytes(c->cfg.n_per_pe)) != hipSuccess)
             rc = PF_EHIP;
@@ -1161,7 +1165,7 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
     if (K == 0) {
         for (uint32_t i = 0; i < 4 * F; ++i) host_out[i] = 0.0;
     } else {
-        void *fn = pick_adjoint_kernel(c->ppt, c->half);
+        void *fn = pick_adjoint_kernel(c->adj_ppt, c->half);
         if (!fn) return PF_EUNSUPPORTED;
         HIP_OK(hipMemsetAsync(c->g_theta, 0, 3 * FM * sizeof(double), c->stream));
         for (uint32_t i = K; i >= 1 && rc == PF_OK; --i) {
@@ -1204,7 +1208,7 @@ int pf_grad_end(pf_ctx *c, const float *d_frames, uint64_t frame_stride, double 
             g.sigma = c->cfg.psf_sigma;
             g.inv_2q = 0.5f / c->cfg.q;
             void *args[] = {&a, &g};
-            if (hipLaunchKernel(fn, dim3((uint32_t)FM), dim3(c->block), args,
+            if (hipLaunchKernel(fn, dim3((uint32_t)FM), dim3(c->adj_block), args,
                                 adjoint_lds_bytes(c->cfg.n_per_pe), c->stream) != hipSuccess)
                 rc = PF_EHIP;
         }

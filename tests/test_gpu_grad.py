@@ -37,6 +37,9 @@ CASES = {
                                            n_per_pe=256), frames=6),
     "arna_2x4096": dict(over=dict(mode=O.MODE_ARNA, n_pe=2, n_per_pe=4096), frames=5),
     "rna_border_3x1000": dict(over=dict(n_pe=3, n_per_pe=1000, width=40, height=40), frames=6),
+    # forward iterations with several PEs per workgroup (the adjoint is the same)
+    "grouped_arna_2x8x128": dict(over=dict(mode=O.MODE_ARNA, n_filters=2, n_pe=8, n_per_pe=128,
+                                           pes_per_wg=4), frames=8),
     # the differentiable workload's shape: 2^20 particles over 256 PEs, 512 x 512
     "c5_arna_256x4096": dict(workload="arna_grad_512_256x4096", over={}, frames=12),
 }
