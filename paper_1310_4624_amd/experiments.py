@@ -257,7 +257,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling",
                                      "batch", "infoshare-study"])
-    ap.add_argument("--out", default="", help="infoshare-study: also write the JSON here")
+    ap.add_argument("--out", default="",
+                    help="infoshare-study, rmse40, scaling: also write the results (with the "
+                         "command line) as JSON here")
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
     ap.add_argument("--ring-groups", type=int, default=0)
     ap.add_argument("--modes", default="arna,rna10,rna50,rna0")
@@ -274,6 +276,16 @@ def main():
                          "workgroup)")
     args = ap.parse_args()
     out = []
+    command = "python -m paper_1310_4624_amd.experiments " + " ".join(sys.argv[1:])
+
+    def emit(r):
+        out.append(r)
+        print(json.dumps(r), flush=True)
+
+    def store():
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps({"command": command, "records": out}, indent=1) + "\n")
     if args.what == "infoshare-study":
         r = infoshare_study(seeds=args.seeds, modes=tuple(args.modes.split(",")),
                             n_pe=args.n_pe, n_per_pe=args.n_per_pe, steps=args.steps or 200)
@@ -309,9 +321,9 @@ def main():
         for n_pe in (24, 96, 384, 1536, 6144):
             for s in range(args.seeds):
                 for mode in args.modes.split(","):
-                    r = tracking(mode, seq_seed=1000 + s, filter_seed=1 + s,
-                                 steps=args.steps or 50, n_pe=n_pe, n_per_pe=40)
-                    print(json.dumps(r), flush=True)
+                    emit(tracking(mode, seq_seed=1000 + s, filter_seed=1 + s,
+                                  steps=args.steps or 50, n_pe=n_pe, n_per_pe=40))
+        store()
         return
     if args.what == "scaling":
         if args.shapes:   # "n_pe:BxP,...": given launch shapes only
@@ -319,14 +331,15 @@ def main():
                 n_pe, shape = item.split(":")
                 bs, ppw = shape.split("x")
                 for mode in args.modes.split(","):
-                    print(json.dumps(scaling(mode, int(n_pe), block_size=int(bs),
-                                             pes_per_wg=int(ppw))), flush=True)
+                    emit(scaling(mode, int(n_pe), block_size=int(bs), pes_per_wg=int(ppw)))
+            store()
             return
         for n_pe in (256, 512, 1024, 2048, 4096, 8192):
             for mode in args.modes.split(","):
-                print(json.dumps(scaling(mode, n_pe)), flush=True)
+                emit(dict(scaling(mode, n_pe), shape="default"))
                 if args.tuned:
-                    print(json.dumps(scaling(mode, n_pe, tune=True)), flush=True)
+                    emit(dict(scaling(mode, n_pe, tune=True), shape="tuned"))
+        store()
         return
     for s in range(args.seeds):
         for mode in args.modes.split(","):
