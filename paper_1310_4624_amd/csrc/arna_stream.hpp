@@ -117,6 +117,34 @@ __device__ __forceinline__ TileView load_tile(const StepArgs &a, const double *x
     return v;
 }
 
+// Division by a divisor that is the same in every lane, with one multiply:
+// m = floor(2^32 / d) gives floor(n m / 2^32) = floor(n / d) or one less
+// (the error n (2^32 - d m) / (d 2^32) is below n / 2^32 < 1), fixed by one
+// remainder test.  d = 1 is taken apart (m would not fit).
+struct Div32 {
+    uint32_t d, m;
+};
+__device__ __forceinline__ Div32 div32_make(uint32_t d) {
+    return Div32{d, d > 1 ? (uint32_t)(0x100000000ull / d) : 0u};
+}
+__device__ __forceinline__ uint32_t div32(uint32_t n, const Div32 &v) {
+    if (v.d == 1) return n;
+    uint32_t q = __umulhi(n, v.m);
+    if (n - q * v.d >= v.d) ++q;
+    return q;
+}
+
+// received_from() for N_p <= 65536 in 32-bit arithmetic (every intermediate
+// is below N_p^2 <= 2^32) with the divisions by N_p and N_ex as above.
+__device__ __forceinline__ uint32_t received_from32(uint32_t s, const Prologue &p, uint32_t np,
+                                                    const Div32 &by_np, const Div32 &by_nex) {
+    if (p.nex == 0) return kNoSlot;
+    const uint32_t sn = s * p.nex;
+    const uint32_t t = sn <= p.c_own ? 0u : div32(sn - p.c_own + np - 1, by_np);
+    if (t >= p.nex || div32(t * np + p.c_own, by_nex) != s) return kNoSlot;
+    return div32(t * np + p.c_pred, by_nex);
+}
+
 // The prologue's results, the same in every lane of a wave, to scalar registers.
 __device__ __forceinline__ Prologue uniform_prologue(const Prologue *pp) {
     Prologue p = *pp;
@@ -146,9 +174,10 @@ __device__ __forceinline__ float pass_a(const StepArgs &a, const Prologue &p, ui
     const bool trace = D && D->t_q;
     float umax = -INFINITY;
     bool bad = false;
+    const Div32 by_np = div32_make(np), by_nex = div32_make(p.nex ? p.nex : 1u);
 #pragma unroll 1
     for (uint32_t s = s0; s < s1; s += step) {
-        const uint32_t r = received_from(s, p, np);
+        const uint32_t r = received_from32(s, p, np, by_np, by_nex);
         const uint32_t blk = (r == kNoSlot) ? pe_base : pred_base;   // PE whose slot it takes
         const uint32_t sb = blk + ((r == kNoSlot) ? s : r);          // that resampled slot
         const float lam = (r == kNoSlot) ? p.lam_own : p.lam_pred;
