@@ -31,6 +31,10 @@ CASES = [
          fixed_ratio=0.5, noise_sigma=1.0, seed=64),
     dict(BASE, n_filters=1, n_pe=3, n_per_pe=200, width=64, height=64, mode=1, lik_mode=0,
          patch=7, seed=65),                                      # launched alone inside the run
+    dict(BASE, n_filters=1, n_pe=6, n_per_pe=128, width=96, height=80, mode=1, lik_mode=0,
+         pes_per_wg=4, seed=66),                                 # several PEs per workgroup
+    dict(BASE, n_filters=1, n_pe=2, n_per_pe=5000, width=96, height=96, mode=1, lik_mode=0,
+         seed=67),                                               # split PEs
 ]
 
 
