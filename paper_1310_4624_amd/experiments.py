@@ -66,11 +66,13 @@ def infoshare(mode: str, seq_seed: int = 1000, filter_seed: int = 1, n_pe: int =
 
 
 def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int = 100,
-             seq=None, workload: str = "arna_tracking_512_4x64x4096", **over) -> dict:
+             seq=None, workload: str = "arna_tracking_512_4x64x4096", q_true=None,
+             **over) -> dict:
     wl = workload
     mflag, ratio = MODES[mode]
     cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, seed=filter_seed, **over)
-    seq = seq if seq is not None else synth.make_sequence(wl, seed=seq_seed, frames=steps)
+    seq = seq if seq is not None else synth.make_sequence(wl, seed=seq_seed, frames=steps,
+                                                          q_true=q_true)
     frames = _frames(seq)
     F = cfg["n_filters"]
     tr = Tracker(cfg, seq.initial_truth()[:F])
@@ -83,6 +85,8 @@ def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int =
     tr.close()
     err2 = np.array(err2)
     return dict(mode=mode, workload=wl, n_pe=cfg["n_pe"], n_per_pe=cfg["n_per_pe"],
+                q_true=q_true if q_true is not None
+                else synth.WORKLOADS[wl]["seq"].get("q_true", cfg["q"]),
                 seq_seed=seq_seed, filter_seed=filter_seed, steps=len(err2),
                 rmse_per_spot=np.sqrt(err2.mean(axis=0)).tolist(),
                 rmse=float(np.sqrt(err2.mean())), mean_n_ex=np.mean(n_ex, axis=0).tolist())
@@ -258,7 +262,7 @@ def main():
     ap.add_argument("what", choices=["infoshare", "curves", "tracking", "rmse40", "scaling",
                                      "batch", "infoshare-study"])
     ap.add_argument("--out", default="",
-                    help="infoshare-study, rmse40, scaling: also write the results (with the "
+                    help="infoshare-study, rmse40, scaling, tracking: also write the results (with the "
                          "command line) as JSON here")
     ap.add_argument("--workload", default="arna_tracking_512_4x64x4096")
     ap.add_argument("--ring-groups", type=int, default=0)
@@ -271,6 +275,9 @@ def main():
     ap.add_argument("--shapes", default="",
                     help="scaling: only these PE counts and launch shapes, as n_pe:BxP,... "
                          "(B = block_size, P = pes_per_wg; 0x0 = the defaults)")
+    ap.add_argument("--q-true", type=float, default=None,
+                    help="tracking: process noise of the true trajectories (default: the "
+                         "workload's)")
     ap.add_argument("--tuned", action="store_true",
                     help="scaling: also the autotuner's launch shape (workgroup size, PEs per "
                          "workgroup)")
@@ -355,9 +362,11 @@ def main():
                                                if i <= len(r["fraction_within"])}}
             else:
                 r = tracking(mode, seq_seed=1000 + s, filter_seed=1 + s,
-                             steps=args.steps or 100, workload=args.workload)
-            out.append(r)
-            print(json.dumps(r), flush=True)
+                             steps=args.steps or 100, workload=args.workload,
+                             q_true=args.q_true)
+            emit(r)
+    if args.what == "tracking":
+        store()
 
 
 if __name__ == "__main__":

@@ -194,15 +194,18 @@ def render_poisson(truth_k, width, height, psf_sigma, background, rng):
     return rng.poisson(lam).astype(np.float32)
 
 
-def make_sequence(workload: str, seed: int = 1000, frames: int | None = None) -> Sequence:
-    """Frames and truth for a named workload (sequence seeds 1000.. by convention)."""
+def make_sequence(workload: str, seed: int = 1000, frames: int | None = None,
+                  q_true: float | None = None) -> Sequence:
+    """Frames and truth for a named workload (sequence seeds 1000.. by convention);
+    q_true overrides the process noise of the true trajectories."""
     w = WORKLOADS[workload]
     sq, fl = w["seq"], w["filter"]
     K = sq["frames"] if frames is None else frames
     rng = np.random.Generator(np.random.PCG64(seed))
+    q = q_true if q_true is not None else sq.get("q_true", fl["q"])
     truth = trajectories(rng, len(sq["intensities"]), K, sq["width"], sq["height"],
                          sq["intensities"], sq["motion"], sq["speed"], sq["start_box"],
-                         sq["margin"], sq["min_sep"], q=sq.get("q_true", fl["q"]))
+                         sq["margin"], sq["min_sep"], q=q)
     out = np.zeros((K, sq["height"], sq["width"]), np.float32)
     for k in range(1, K + 1):
         if sq.get("noise") == "poisson":
