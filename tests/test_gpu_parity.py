@@ -593,7 +593,11 @@ def test_edge_single_pe_single_particle_and_full_exchange():
     ft = torch.from_numpy(frame).cuda()
     for over in [dict(n_pe=1, n_per_pe=64, mode=1), dict(n_pe=3, n_per_pe=1, mode=0,
                                                         fixed_ratio=1.0),
-                 dict(n_pe=4, n_per_pe=50, mode=0, fixed_ratio=1.0)]:
+                 dict(n_pe=4, n_per_pe=50, mode=0, fixed_ratio=1.0),
+                 dict(n_pe=3, n_per_pe=1, mode=0, fixed_ratio=1.0, pes_per_wg=2),
+                 dict(n_pe=4, n_per_pe=50, mode=0, fixed_ratio=1.0, pes_per_wg=4),
+                 dict(n_pe=2, n_per_pe=4097, mode=0, fixed_ratio=1.0),
+                 dict(n_pe=1, n_per_pe=6000, mode=1)]:
         cfg = dict(n_filters=1, width=40, height=40, patch=9, init_mode=0, lik_mode=0,
                    initial_ratio=0.1, eff_cutoff=0.99, psf_sigma=1.5, background=5.0,
                    noise_sigma=2.0, q=0.5, sigma_I=0.5, seed=21, fixed_ratio=0.1)
@@ -625,12 +629,15 @@ def test_nan_pixel_sets_sticky_numeric_error():
     g.close()
 
 
-def test_dead_pe_gets_no_mass():
+@pytest.mark.parametrize("n_p,over", [(64, {}), (64, dict(pes_per_wg=2)), (5000, {})])
+def test_dead_pe_gets_no_mass(n_p, over):
+    """A PE without mass (L = -inf) keeps none: one PE per workgroup, several
+    PEs per workgroup, split PEs."""
     p = pf()
-    cfg = dict(n_filters=1, n_pe=4, n_per_pe=64, width=40, height=40, seed=2, mode=0,
-               fixed_ratio=0.0)
+    cfg = dict(n_filters=1, n_pe=4, n_per_pe=n_p, width=40, height=40, seed=2, mode=0,
+               fixed_ratio=0.0, **over)
     rng = np.random.Generator(np.random.PCG64(4))
-    state = synth.random_state(rng, 1, 4, 64, 40, 40, spread=1.0, centre=[[20, 20]])
+    state = synth.random_state(rng, 1, 4, n_p, 40, 40, spread=1.0, centre=[[20, 20]])
     L = np.array([[0.0, -np.inf, 0.0, 0.0]])
     g = p.Tracker(cfg, np.zeros((1, 5), np.float32))
     g.set_state(state, L, step=3)
