@@ -155,6 +155,41 @@ def gpu_leg(workload: str, steps: int, warmup: int, seed: int, probe: int, ring_
                 traj_steps=[int(tj["step"][0][0]), int(tj["step"][-1][0])] if steps else [])
 
 
+def phase_leg(workload: str, seed: int, spread: int = 20, converged: int = 64):
+    """The information-sharing workload from its start, in its two phases:
+    iterations 1..spread, while the PEs are still spread over the frame (most
+    patches read the frame), and the next `converged` iterations, once they
+    share the spot (patches read the LDS tile).  Each phase is one pf_run_traj
+    call between two events; a separate context loads the kernels first."""
+    import torch
+    from paper_1310_4624_amd import TRAJ_RECORD_BYTES, Tracker, synth
+
+    cfg = synth.filter_config(workload, seed=seed)
+    seq = synth.make_sequence(workload, seed=1000, frames=spread + converged)
+    frames = torch.from_numpy(seq.frames).cuda()
+    F = cfg["n_filters"]
+    traj = torch.empty(max(spread, converged) * F * TRAJ_RECORD_BYTES, dtype=torch.uint8,
+                       device="cuda")
+    stream = torch.cuda.current_stream()
+    warm = Tracker(cfg, seq.initial_truth()[:F])
+    warm.run_traj(frames[:2], traj)
+    warm.close()
+    tr = Tracker(cfg, seq.initial_truth()[:F])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    tr.run_traj(frames[:spread], traj)
+    ev[1].record(stream)
+    tr.run_traj(frames[spread:spread + converged], traj)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    tr.close()
+    return {"spread_iterations": [1, spread],
+            "spread_ms_per_step": ev[0].elapsed_time(ev[1]) / spread,
+            "converged_iterations": [spread + 1, spread + converged],
+            "converged_ms_per_step": ev[1].elapsed_time(ev[2]) / converged}
+
+
 def grad_leg(workload: str, frames_n: int, seed: int):
     """Cost of the gradient: K iterations forward, then the same K iterations
     recorded plus the reverse sweep (pf_grad_end), on the same frames and
@@ -359,6 +394,9 @@ def main():
                 "ms_per_step_without_master_record": x["plain_ms"], "n_particles": x["n"],
                 "kernel_ms": x["kernel_ms"], "roofline_frac": x["achieved"] / HBM_PEAK_GBS}
             for w, x in ((args.workload, h), (args.second_workload, h2))}
+        if synth.WORKLOADS[args.second_workload]["filter"].get("init_mode") == 1:
+            line["workloads"][args.second_workload]["phases"] = phase_leg(
+                args.second_workload, args.seed)
     if args.grad_frames:
         gl = grad_leg(args.grad_workload, args.grad_frames, args.seed)
         line["fwd_bwd_over_fwd"] = gl["fwd_bwd_over_fwd"]
