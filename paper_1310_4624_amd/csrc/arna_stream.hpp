@@ -5,7 +5,10 @@
 //     barriers, and their log-weights live in LDS;
 //   * one PE whose particles do not fit the LDS stage of k_step
 //     (PF_MAX_PER_PE_LDS < N_p <= PF_MAX_PER_PE): the log-weights go to a
-//     per-context HBM array.
+//     per-context HBM array;
+//   * such a PE split over several workgroups, when a context has fewer PEs
+//     than compute units (the split kernels at the end of this file: the
+//     same passes as three launches).
 // The data layout is k_step's (propagated particles plus a 16-bit ancestor
 // slot), so the kernels compute the same iteration on the same buffers: Q,
 // ancestors and every traced value are k_step's bit for bit, and only the
