@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -52,11 +53,21 @@ def algorithmic_bytes(n_particles: int, width: int, height: int) -> float:
     return STATE_BYTES * n_particles + 4.0 * width * height
 
 
+def code_tokens(text: str) -> str:
+    """C++ source without its comments and with runs of white space made one
+    space (string literals in the kernel sources hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sha() -> str:
+    """Hash of the k_step sources' code (comments and layout excluded), which
+    ties the stored counters to the kernel they were taken on."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

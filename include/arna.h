@@ -67,8 +67,8 @@ enum { PF_DEBUG_TRACE = 1,    /* keep Q, ancestors, propagated state, ... of the
  * same results up to the summation order of the FP64 PE sums; with fewer than
  * 256 PEs each PE is split over several workgroups): such contexts take no
  * block_size other than 0 or 1024, no pes_per_wg above 1 (PF_EINVAL), no
- * PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT, fewer than 2048 PEs and no
- * gradient recording (PF_EUNSUPPORTED), and hold N more floats of device
+ * PF_DEBUG_LINEAGE, no PF_LAUNCH_PERSISTENT and no gradient recording
+ * (PF_EUNSUPPORTED), and hold N more floats of device
  * memory (the log-weights of the iteration). */
 #define PF_MAX_PER_PE_LDS 4096u
 #define PF_MAX_PATCH 15u
@@ -120,10 +120,15 @@ typedef struct {
                                  * only received slots are read back, and the PEs of a filter
                                  * meet at a barrier between iterations instead of a launch
                                  * boundary.  It needs a 9 x 9 patch or point data, no debug
-                                 * flag, M < 2048, and F M workgroups resident at once
+                                 * flag, M < 2048 (else PF_EUNSUPPORTED), and F M
+                                 * workgroups resident at once
                                  * (cooperative launch; e.g. F M <= 256 at N_p = 4096 on
                                  * MI355X).  Results are bitwise those of one launch per
-                                 * iteration.  Iterations that record a gradient tape or
+                                 * iteration below 512 PEs (from 512 PEs on, one launch
+                                 * per iteration is followed by the master step computed
+                                 * once per filter, with another FP64 summation order;
+                                 * a multi-iteration context keeps the order of its own
+                                 * launches).  Iterations that record a gradient tape or
                                  * replay forced choices always run one launch each.  The
                                  * barrier costs less than a launch boundary only for small
                                  * contexts (about 10-15% faster up to 64 PEs), and the

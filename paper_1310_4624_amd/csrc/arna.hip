@@ -88,7 +88,7 @@ struct pf_ctx {
     uint64_t ring_base;
     bool ring_valid;
     uint32_t *err, *nex_used;
-    // master records (used when M >= kMasterMinPE), ping-pong like the records
+    // master records (uses_master), ping-pong like the records
     MasterRec *mrec[2];
     uint32_t *arrive;              // (for a master step in the step's last workgroup)
     // multi-iteration launches (k_run): kernel, or NULL when the context
@@ -192,8 +192,19 @@ int noalloc_setup(int dev) {
 // the agent-scope release every workgroup then needs before counting itself
 // in cost more than the launch, measured on MI355X with several PEs per
 // workgroup at 2^20 particles: 2048 x 512 52.1 -> 47.0 us per iteration,
-// 4096 x 256 55.6 -> 53.2, 8192 x 128 81.3 -> 74.8.
-constexpr uint32_t kMasterMinPE = 2048;
+// 4096 x 256 55.6 -> 53.2, 8192 x 128 81.3 -> 74.8.  The threshold, measured
+// at 2^20 (us per iteration with the threshold at 2048 / 512): 512 x 2048
+// 48.9 / 46.1, 1024 x 1024 95.5 / 68.3 (one PE per workgroup) and 46.3 / 43.0
+// (two); 256 x 4096 33.3 with either, 37.6 with the threshold at 256.
+constexpr uint32_t kMasterMinPE = 512;
+// Multi-iteration launches (k_run) keep the master step in every PE's
+// prologue: they take fewer PEs than this and no master record.
+constexpr uint32_t kRunMaxPE = 2048;
+
+// Whether a context keeps once-per-filter master records.
+bool uses_master(const pf_config *c) {
+    return c->n_pe >= kMasterMinPE && c->launch != PF_LAUNCH_PERSISTENT;
+}
 
 #define HIP_OK(expr)                                      \
     do {                                                  \
@@ -447,12 +458,11 @@ int validate(const pf_config *c) {
         if ((c->debug & PF_DEBUG_LINEAGE) || c->launch == PF_LAUNCH_PERSISTENT)
             return PF_EUNSUPPORTED;
     }
+    if (c->launch == PF_LAUNCH_PERSISTENT && c->n_pe >= kRunMaxPE) return PF_EUNSUPPORTED;
     if (c->n_per_pe > PF_MAX_PER_PE_LDS) {
-        // one streamed PE per workgroup of 1024 threads, without the
-        // once-per-filter master record
+        // one streamed PE per workgroup of 1024 threads
         if (c->pes_per_wg > 1) return PF_EINVAL;
         if (c->block_size && c->block_size != kStreamBlock) return PF_EINVAL;
-        if (c->n_pe >= kMasterMinPE) return PF_EUNSUPPORTED;
     } else if (c->pes_per_wg > 1) {
         // ppw groups of whole waves, at most 4 slots per thread
         const uint32_t ppw = c->pes_per_wg;
@@ -661,7 +671,7 @@ bool run_allowed(const pf_ctx *c) {
 int launch_global(pf_ctx *c, pf_master_t *out) {
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     // fewer PEs: one wave per filter, in the order of the step's prologue
-    if (c->cfg.n_pe < kMasterMinPE)
+    if (!c->mrec[0])
         hipLaunchKernelGGL(k_global_wave, dim3(c->cfg.n_filters), dim3(kWave), 0, c->stream,
                            cur_rec(c), out, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
                            c->fixed_nex, c->cutoff_ppm, (const uint32_t *)c->nex_used,
@@ -674,10 +684,10 @@ int launch_global(pf_ctx *c, pf_master_t *out) {
     return PF_OK;
 }
 
-// With traj, the master step of every iteration goes to traj[i][F]: for
-// fewer than kMasterMinPE PEs the step of iteration i + 1 writes row i from
-// its prologue and one k_global_wave launch after the run writes the last
-// row; for more, a k_global launch follows every step.  Either way the
+// With traj, the master step of every iteration goes to traj[i][F]: without
+// master records the step of iteration i + 1 writes row i from its prologue
+// and one k_global_wave launch after the run writes the last row; with them
+// (and for split PEs), a global-estimate launch follows every step.  Either way the
 // iterations run one launch each.
 int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out,
               pf_master_t *traj = nullptr) {
@@ -875,7 +885,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     }
     if (rc == PF_OK && cfg->mode == PF_MODE_ARNA && M > 1)
         rc = dev_alloc(&c->ring_tab, (size_t)kRingSteps * c->FM);
-    if (rc == PF_OK && M >= kMasterMinPE) {
+    if (rc == PF_OK && uses_master(cfg)) {
         rc = dev_alloc(&c->mrec[0], F);
         if (rc == PF_OK) rc = dev_alloc(&c->mrec[1], F);
         if (rc == PF_OK) rc = dev_alloc(&c->arrive, F);

@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, pf_mast
     }
 }
 
-// k_global for M < kMasterMinPE with one wave per filter: the master step in
+// k_global for contexts without master records, one wave per filter: the master step in
 // the order of prologue_wave's sums (records in chunks of 64 lanes, the first
 // kCached chunks, then the rest; wave butterflies), so that a trajectory row
 // written by the prologue and this kernel's record agree bit for bit.

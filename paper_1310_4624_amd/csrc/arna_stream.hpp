@@ -30,9 +30,9 @@
 //     the lanes' first ranks.  These are the ancestors k_step finds from its
 //     offspring marks (rank j goes to min { i : N_p C_i > j T + V }), with
 //     O(N_p) work however degenerate the weights are;
-//   then thread 0 writes the workgroup's PE records (steps 8-9) and, with the
-//   once-per-filter master record (M >= 2048), the last workgroup of the
-//   filter computes it.
+//   then thread 0 writes the workgroup's PE records (steps 8-9) and, when
+//   asked (StepArgs.mout), the last workgroup of the filter computes the
+//   once-per-filter master record.
 #pragma once
 
 #include "arna_kernels.hpp"

@@ -111,11 +111,12 @@ def _init(L, **kw):
     (dict(block_size=2048), nat.PF_EINVAL),            # above 1024
     (dict(n_per_pe=4096, block_size=512), nat.PF_EINVAL),   # 4 slots per thread do not cover N_p
     # PEs beyond the LDS stage: the streaming kernel's 1024 threads only, and
-    # none of lineage tags, multi-iteration launches, 2048 or more PEs
+    # none of lineage tags, multi-iteration launches
     (dict(n_per_pe=5000, block_size=512), nat.PF_EINVAL),
     (dict(n_per_pe=5000, debug=nat.PF_DEBUG_LINEAGE), nat.PF_EUNSUPPORTED),
     (dict(n_per_pe=5000, launch=nat.PF_LAUNCH_PERSISTENT), nat.PF_EUNSUPPORTED),
-    (dict(n_per_pe=8192, n_pe=2048), nat.PF_EUNSUPPORTED),
+    # multi-iteration launches take fewer than 2048 PEs
+    (dict(n_per_pe=4, n_pe=2048, launch=nat.PF_LAUNCH_PERSISTENT), nat.PF_EUNSUPPORTED),
     # several PEs per workgroup: whole waves per PE, 4 slots per thread at most
     (dict(pes_per_wg=17), nat.PF_EINVAL),
     (dict(n_per_pe=5000, pes_per_wg=2), nat.PF_EINVAL),

@@ -181,17 +181,19 @@ def seeded_case(name):
         state = synth.random_state(rng, F, M, n_p, cfg["width"], cfg["height"], spread=spread,
                                    centre=centre, I0=10.0)
         return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (F, M))
-    elif name == "arna_1x256x4100":
-        # 256 streamed PEs: one workgroup per PE (no split), every PE compared
-        cfg = dict(n_filters=1, n_pe=256, n_per_pe=4100, width=256, height=256, patch=9,
+    elif name in ("arna_1x256x4100", "arna_1x512x4100"):
+        # streamed PEs: one workgroup per PE (no split), every PE compared;
+        # at 512 PEs the master step is computed once per filter
+        M = 256 if name == "arna_1x256x4100" else 512
+        cfg = dict(n_filters=1, n_pe=M, n_per_pe=4100, width=256, height=256, patch=9,
                    mode=1, init_mode=0, lik_mode=0, fixed_ratio=0.1, initial_ratio=0.1,
                    eff_cutoff=0.99, psf_sigma=1.5, background=5.0, noise_sigma=2.0, q=0.5,
-                   sigma_I=0.5, seed=SEED + 14)
+                   sigma_I=0.5, seed=SEED + (14 if M == 256 else 15))
         truth = np.array([[[100.3, 120.6, 0, 0, 12.0]]])
         frame = synth.render(truth[0], 256, 256, 1.5, 5.0, 2.0, rng)
-        state = synth.random_state(rng, 1, 256, 4100, 256, 256, spread=3.0,
+        state = synth.random_state(rng, 1, M, 4100, 256, 256, spread=3.0,
                                    centre=truth[0, :, :2], I0=10.0)
-        return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (1, 256))
+        return cfg, np.asarray(frame, np.float32), state, rng.normal(0.0, 3.0, (1, M))
     elif name in ("arna_2x4x16384", "arna_1x3x65536"):
         # PEs beyond the LDS stage (the streaming step): 2 spots on 256^2
         # around which the particles sit, and 1 spot on 512^2 with the
@@ -286,7 +288,7 @@ def test_one_step_parity(name, k_done):
 
 
 @pytest.mark.parametrize("name", ["arna_2x4x16384", "arna_1x3x65536", "poisson_rna_1x2x20000",
-                                  "point_arna_2x3x5000", "arna_1x256x4100"])
+                                  "point_arna_2x3x5000", "arna_1x256x4100", "arna_1x512x4100"])
 @pytest.mark.parametrize("k_done", [0, 7])
 def test_one_step_parity_streaming(name, k_done):
     """PEs of more than 4096 particles, every PE: split over several
