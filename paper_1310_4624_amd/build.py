@@ -15,7 +15,7 @@ SRC = os.path.join(PKG, "csrc", "arna.hip")
 SRC_RUN = os.path.join(PKG, "csrc", "arna_run.hip")
 DEPS = [SRC, SRC_RUN, os.path.join(PKG, "csrc", "arna_device.hpp"),
         os.path.join(PKG, "csrc", "arna_kernels.hpp"), os.path.join(PKG, "csrc", "arna_adjoint.hpp"),
-        os.path.join(PKG, "csrc", "arna_stream.hpp"),
+        os.path.join(PKG, "csrc", "arna_stream.hpp"), os.path.join(PKG, "csrc", "arna_master.hpp"),
         os.path.join(ROOT, "include", "arna.h")]
 LIB = os.path.join(PKG, "libarna.so")
 ARCH = "gfx950"

@@ -31,6 +31,7 @@
 #include "arna_kernels.hpp"
 #include "arna_adjoint.hpp"
 #include "arna_stream.hpp"
+#include "arna_master.hpp"
 
 using namespace arna;
 
@@ -591,7 +592,7 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame, pf_master_t *traj_
 int refresh_master(pf_ctx *c, int which) {
     if (!c->mrec[0]) return PF_OK;
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(kMasterThreads), 0, c->stream,
                        c->rec[which], c->mrec[which], c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
                        c->fixed_nex, c->cutoff_ppm);
     HIP_OK(hipGetLastError());
@@ -633,9 +634,9 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
     HIP_OK(hipLaunchKernel(fn, dim3(c->n_wg), dim3(c->block), args, c->lds, c->stream));
     if (c->mrec[0]) {
         // the master step of this iteration from the records just written
-        hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(256), 0, c->stream, a.rout,
-                           c->mrec[1 - c->cur], c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
-                           c->fixed_nex, c->cutoff_ppm);
+        hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(kMasterThreads), 0, c->stream,
+                           a.rout, c->mrec[1 - c->cur], c->cfg.n_pe, c->cfg.n_per_pe,
+                           c->cfg.mode, c->fixed_nex, c->cutoff_ppm);
         HIP_OK(hipGetLastError());
     }
     advance(c, k);

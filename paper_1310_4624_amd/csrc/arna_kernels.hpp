@@ -256,15 +256,6 @@ __device__ void master_block(const pf_pe_record *R, uint32_t M, uint32_t np, uin
     }
 }
 
-// Master records of every filter (after initialization or a state load).
-__global__ __launch_bounds__(256) void k_master(const pf_pe_record *rec, MasterRec *out,
-                                                uint32_t M, uint32_t np, uint32_t mode,
-                                                uint32_t fixed_nex, uint32_t cutoff_ppm) {
-    __shared__ double red[kRedDoubles];
-    master_block(rec + (size_t)blockIdx.x * M, M, np, mode, fixed_nex, cutoff_ppm, red,
-                 out + blockIdx.x);
-}
-
 // Step 3: PE m sends its slots s_t(m) = floor((t N_p + c_m) / N_ex), t < N_ex,
 // and refills them with the slots s_t(pred(m)) that pred(m) sends.  The map
 // recv[s_t(m)] = s_t(pred(m)) is built in LDS (0xFFFF = slot keeps its own

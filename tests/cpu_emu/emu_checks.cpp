@@ -11,6 +11,7 @@
 //                  compared after each iteration; then contexts of up to
 //                  65536 particles per PE through pf_step, their ancestors
 //                  checked against systematic resampling of the traced weights
+//   master         k_master against master_block, bit for bit
 #include "src/arna.hip"
 #include <algorithm>
 #include <random>
@@ -470,6 +471,66 @@ static int stream_main() {
     return bad ? 2 : 0;
 }
 
+// master_block, the in-kernel form of the master record, on the workgroup
+// size of k_master.
+__global__ void k_master_ref(const pf_pe_record *rec, MasterRec *out, uint32_t M, uint32_t np,
+                             uint32_t mode, uint32_t fixed_nex, uint32_t cutoff_ppm) {
+    __shared__ double red[kRedDoubles];
+    master_block(rec + (size_t)blockIdx.x * M, M, np, mode, fixed_nex, cutoff_ppm, red,
+                 out + blockIdx.x);
+}
+
+// k_master (every log-mass of a thread loaded before the reductions) against
+// master_block, bit for bit: random masses, PEs without mass, filters without
+// mass, one PE holding it all; ragged M up to PF_MAX_PE.
+static int master_main() {
+    struct MC { uint32_t F, M, np, mode, kind; };
+    const MC cases[] = {{1, 1, 64, 1, 0},     {2, 3, 100, 1, 1},    {1, 255, 4096, 1, 0},
+                        {1, 256, 4096, 1, 1}, {3, 300, 77, 0, 0},   {1, 2100, 4, 1, 1},
+                        {1, 8192, 128, 1, 0}, {2, 8192, 128, 1, 3}, {2, 600, 4100, 1, 2},
+                        {1, 7999, 16, 1, 1}};
+    std::mt19937_64 rng(5);
+    std::normal_distribution<double> Nd(0, 3);
+    std::uniform_int_distribution<int> coin(0, 3);
+    int bad = 0;
+    for (const MC &mc : cases) {
+        const size_t n = (size_t)mc.F * mc.M;
+        std::vector<pf_pe_record> rec(n);
+        memset(rec.data(), 0, n * sizeof(pf_pe_record));
+        for (size_t i = 0; i < n; ++i) {
+            double L = Nd(rng);
+            if (mc.kind == 1 && coin(rng) == 0) L = -INFINITY;   // PEs without mass
+            if (mc.kind == 2) L = -INFINITY;                      // no mass at all
+            if (mc.kind == 3) L = (i % mc.M == 17) ? 0.0 : -800.0;
+            rec[i].log_mass = L;
+        }
+        pf_pe_record *d_rec;
+        MasterRec *d_a, *d_b;
+        hipMalloc(&d_rec, n * sizeof(pf_pe_record));
+        hipMalloc(&d_a, mc.F * sizeof(MasterRec));
+        hipMalloc(&d_b, mc.F * sizeof(MasterRec));
+        memcpy(d_rec, rec.data(), n * sizeof(pf_pe_record));
+        memset(d_a, 0xAB, mc.F * sizeof(MasterRec));
+        memset(d_b, 0xCD, mc.F * sizeof(MasterRec));
+        const uint32_t fixed_nex = mc.np / 10, cutoff = 990000;
+        hipLaunchKernelGGL(k_master, dim3(mc.F), dim3(kMasterThreads), 0, nullptr, d_rec, d_a,
+                           mc.M, mc.np, mc.mode, fixed_nex, cutoff);
+        hipLaunchKernelGGL(k_master_ref, dim3(mc.F), dim3(kMasterThreads), 0, nullptr, d_rec, d_b,
+                           mc.M, mc.np, mc.mode, fixed_nex, cutoff);
+        hipDeviceSynchronize();
+        const bool eq = memcmp(d_a, d_b, mc.F * sizeof(MasterRec)) == 0;
+        fprintf(stderr, "master F=%u M=%u np=%u mode=%u kind=%u: %s (log W %.17g, N_ex %u)\n",
+                mc.F, mc.M, mc.np, mc.mode, mc.kind, eq ? "equal" : "DIFFERENT", d_a[0].lglob,
+                d_a[0].nex_next);
+        bad += !eq;
+        hipFree(d_rec);
+        hipFree(d_a);
+        hipFree(d_b);
+    }
+    fprintf(stderr, bad ? "MASTER MISMATCH\n" : "MASTER EQUAL\n");
+    return bad ? 2 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc > 1 && !strcmp(argv[1], "batch")) {
         if (argc > 4) emu_set_fill(atoi(argv[4]));
@@ -477,6 +538,7 @@ int main(int argc, char **argv) {
     }
     if (argc > 1 && !strcmp(argv[1], "traj")) return traj_main();
     if (argc > 1 && !strcmp(argv[1], "stream")) return stream_main();
-    fprintf(stderr, "usage: %s batch K MODE [FILL] | traj | stream\n", argv[0]);
+    if (argc > 1 && !strcmp(argv[1], "master")) return master_main();
+    fprintf(stderr, "usage: %s batch K MODE [FILL] | traj | stream | master\n", argv[0]);
     return 1;
 }

@@ -83,3 +83,10 @@ def test_streaming_kernel_equals_lds_kernel_and_resamples_exactly(checks):
     # systematic resampling of the traced weights
     rc, err = _run(checks, "stream")
     assert rc == 0 and "STREAM EQUAL" in err, err[-4000:]
+
+
+def test_master_record_kernel_equals_in_kernel_form(checks):
+    # k_master loads a thread's log-masses before reducing them; the record
+    # is bitwise that of master_block with the same workgroup size
+    rc, err = _run(checks, "master")
+    assert rc == 0 and "MASTER EQUAL" in err, err[-4000:]
