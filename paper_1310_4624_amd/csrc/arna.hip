@@ -91,6 +91,7 @@ struct pf_ctx {
     uint32_t *err, *nex_used;
     // master records (uses_master), ping-pong like the records
     MasterRec *mrec[2];
+    double *lm;                    // k_step_flex's log-masses [F M] for k_master, or NULL
     uint32_t *arrive;              // (for a master step in the step's last workgroup)
     // multi-iteration launches (k_run): kernel, or NULL when the context
     // cannot keep all its workgroups resident; barrier counters and wait limit
@@ -501,7 +502,7 @@ void free_all(pf_ctx *c) {
                     c->lin[0], c->lin[1],
                     c->ring_tab, c->err, c->nex_used, c->est, c->t_pred, c->t_q, c->t_anc,
                     c->t_v, c->t_src, c->t_prop, c->t_ell, c->t_lam, c->d_dbg,
-                    c->mrec[0], c->mrec[1], c->arrive, c->bar, c->run_args,
+                    c->mrec[0], c->mrec[1], c->lm, c->arrive, c->bar, c->run_args,
                     c->g_prop, c->g_anc, c->g_rec, c->g_nex, c->g_bar[0], c->g_bar[1], c->g_lbar[0],
                     c->g_lbar[1], c->g_theta, c->g_out, c->u, c->sb.seg_max, c->sb.seg_wq,
                     c->sb.seg_sum};
@@ -591,11 +592,8 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame, pf_master_t *traj_
 // state load), when the context uses them.
 int refresh_master(pf_ctx *c, int which) {
     if (!c->mrec[0]) return PF_OK;
-    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(kMasterThreads), 0, c->stream,
-                       c->rec[which], c->mrec[which], c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
-                       c->fixed_nex, c->cutoff_ppm);
-    HIP_OK(hipGetLastError());
+    HIP_OK(launch_master(c->stream, c->cfg.n_filters, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
+                         c->fixed_nex, c->cutoff_ppm, c->rec[which], nullptr, c->mrec[which]));
     return PF_OK;
 }
 
@@ -630,14 +628,14 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
         advance(c, k);
         return PF_OK;
     }
-    void *args[] = {&a, &c->u, &c->ppw};   // (k_step takes the first only)
+    void *args[] = {&a, &c->u, &c->ppw, &c->lm};   // (k_step takes the first only)
     HIP_OK(hipLaunchKernel(fn, dim3(c->n_wg), dim3(c->block), args, c->lds, c->stream));
     if (c->mrec[0]) {
         // the master step of this iteration from the records just written
-        hipLaunchKernelGGL(k_master, dim3(c->cfg.n_filters), dim3(kMasterThreads), 0, c->stream,
-                           a.rout, c->mrec[1 - c->cur], c->cfg.n_pe, c->cfg.n_per_pe,
-                           c->cfg.mode, c->fixed_nex, c->cutoff_ppm);
-        HIP_OK(hipGetLastError());
+        // (k_step_flex also wrote their log-masses side by side)
+        HIP_OK(launch_master(c->stream, c->cfg.n_filters, c->cfg.n_pe, c->cfg.n_per_pe,
+                             c->cfg.mode, c->fixed_nex, c->cutoff_ppm, a.rout, c->lm,
+                             c->mrec[1 - c->cur]));
     }
     advance(c, k);
     return PF_OK;
@@ -890,6 +888,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
         rc = dev_alloc(&c->mrec[0], F);
         if (rc == PF_OK) rc = dev_alloc(&c->mrec[1], F);
         if (rc == PF_OK) rc = dev_alloc(&c->arrive, F);
+        if (rc == PF_OK && c->flex) rc = dev_alloc(&c->lm, c->FM);
     }
     if (rc == PF_OK) rc = dev_alloc(&c->err, 1);
     if (rc == PF_OK) rc = dev_alloc(&c->nex_used, F);

@@ -1,21 +1,21 @@
 // The once-per-filter master record of Alg. 3 steps 9-10 (Sec. IV-C) for
 // contexts with many PEs: the global log-mass log W_k = log sum_m W_k^(m)
-// (the normalizer of the next iteration's lambda, Eq. 3) and the exchange
-// count that PE_eff = (sum_m W^(m))^2 / sum_m (W^(m))^2 (Eq. 4) gives for the
-// next iteration.
+// (the renormalization of the next iteration's step 4) and the exchange count
+// of Eq. 3 for the next iteration, from PE_eff = (sum_m W^(m))^2 /
+// sum_m (W^(m))^2 (Eq. 4).
 //
-// One workgroup of kMasterThreads threads per filter reads the M records its
-// filter's PEs wrote.  Thread t takes records t, t + kMasterThreads, ... and
+// One workgroup of kMasterThreads threads per filter reads the M log-masses
+// its filter's PEs wrote.  Thread t takes PEs t, t + kMasterThreads, ... and
 // reduces them in that order, as master_block does with the same block size,
 // so the record is bitwise master_block's; but the thread loads all of its
-// log-masses (at most PF_MAX_PE / kMasterThreads) into registers before
-// reducing them, so that their latencies overlap instead of adding up over
-// the two passes (maximum, then the sum of exp(L - max)).  Measured on
-// MI355X (us per launch, one filter, loads issued as they are needed / all
-// first): 512 PEs 5.0 / 5.5, 2048 7.8 / 6.3, 4096 11.8 / 8.2, 8192 19.7 /
-// 12.2.  What remains at many PEs is the read of the log-masses, one per
-// 56-byte record, by a single compute unit (1024 threads instead of 256:
-// 12.0 us at 8192 PEs, and slower below).
+// log-masses into registers before reducing them, so that their latencies
+// overlap instead of adding up over the two passes (maximum, then the sum of
+// exp(L - max)), and k_step_flex writes the log-masses side by side, so that
+// the read is contiguous rather than one 8-byte value per 56-byte record.
+// Measured on MI355X (us per launch, one filter; two passes over the records
+// with the loads issued as needed / this kernel): 512 PEs 5.0 / 4.5, 1024 5.9
+// / 4.8, 2048 7.8 / 6.6, 4096 11.8 / 7.8, 8192 19.7 / 9.9.  (1024 threads
+// instead of 256, from the records: 12.0 us at 8192 PEs, longer below.)
 #pragma once
 
 #include "arna_kernels.hpp"
@@ -26,31 +26,43 @@ constexpr uint32_t kMasterThreads = 256;
 constexpr uint32_t kMasterPerThread = PF_MAX_PE / kMasterThreads;
 static_assert(kMasterPerThread * kMasterThreads == PF_MAX_PE, "PF_MAX_PE records per workgroup");
 
-// Master record of filter blockIdx.x from its M <= PF_MAX_PE records (block
-// of kMasterThreads threads).
+// Master record of filter blockIdx.x from its M <= PER kMasterThreads records
+// (block of kMasterThreads threads).  With lm (the log-masses [F M] the step
+// wrote beside the records) the reads are contiguous: the same values, the
+// same record.  PER only sizes the unrolled loads: every PER covering M gives
+// the same record.
+template <uint32_t PER>
 __global__ __launch_bounds__(kMasterThreads) void k_master(const pf_pe_record *rec,
-                                                           MasterRec *out, uint32_t M,
-                                                           uint32_t np, uint32_t mode,
+                                                           const double *lm, MasterRec *out,
+                                                           uint32_t M, uint32_t np, uint32_t mode,
                                                            uint32_t fixed_nex,
                                                            uint32_t cutoff_ppm) {
     __shared__ double red[kRedDoubles];
-    const pf_pe_record *R = rec + (size_t)blockIdx.x * M;
+    const size_t base = (size_t)blockIdx.x * M;
     const uint32_t tid = threadIdx.x;
-    double L[kMasterPerThread];
+    double L[PER];
+    if (lm) {
 #pragma unroll
-    for (uint32_t j = 0; j < kMasterPerThread; ++j) {
-        const uint32_t i = tid + j * kMasterThreads;
-        L[j] = i < M ? R[i].log_mass : -INFINITY;
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t i = tid + j * kMasterThreads;
+            L[j] = i < M ? lm[base + i] : -INFINITY;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t i = tid + j * kMasterThreads;
+            L[j] = i < M ? rec[base + i].log_mass : -INFINITY;
+        }
     }
     double lmax = -INFINITY;
 #pragma unroll
-    for (uint32_t j = 0; j < kMasterPerThread; ++j) lmax = fmax(lmax, L[j]);
+    for (uint32_t j = 0; j < PER; ++j) lmax = fmax(lmax, L[j]);
     lmax = block_max_d(lmax, red);
     double acc[1] = {0.0};
     uint64_t sd[2] = {0, 0};
     if (lmax != -INFINITY) {
 #pragma unroll
-        for (uint32_t j = 0; j < kMasterPerThread; ++j) {
+        for (uint32_t j = 0; j < PER; ++j) {
             if (tid + j * kMasterThreads < M) {
                 const double e = exp(L[j] - lmax);
                 const uint64_t P = (uint64_t)floor(e * 1048576.0);
@@ -69,6 +81,25 @@ __global__ __launch_bounds__(kMasterThreads) void k_master(const pf_pe_record *r
         r.pad = 0;
         out[blockIdx.x] = r;
     }
+}
+
+// The master records of F filters of M PEs each on stream s: the smallest
+// unrolling that covers M (a short kernel for few PEs).
+inline hipError_t launch_master(hipStream_t s, uint32_t F, uint32_t M, uint32_t np,
+                                uint32_t mode, uint32_t fixed_nex, uint32_t cutoff_ppm,
+                                const pf_pe_record *rec, const double *lm, MasterRec *out) {
+    (void)hipGetLastError();   // clear errors of earlier, unrelated calls
+    const dim3 grid(F), block(kMasterThreads);
+    if (M <= 2 * kMasterThreads)
+        hipLaunchKernelGGL(k_master<2>, grid, block, 0, s, rec, lm, out, M, np, mode, fixed_nex,
+                           cutoff_ppm);
+    else if (M <= 8 * kMasterThreads)
+        hipLaunchKernelGGL(k_master<8>, grid, block, 0, s, rec, lm, out, M, np, mode, fixed_nex,
+                           cutoff_ppm);
+    else
+        hipLaunchKernelGGL(k_master<kMasterPerThread>, grid, block, 0, s, rec, lm, out, M, np,
+                           mode, fixed_nex, cutoff_ppm);
+    return hipGetLastError();
 }
 
 }  // namespace

@@ -321,10 +321,11 @@ __device__ __forceinline__ void fixed_ancestors(const StepArgs &a, uint32_t pe_b
 // multiple of 64; workgroup g of filter f holds PEs g ppw .. g ppw + ppw - 1,
 // the last workgroup of a filter possibly fewer).  ULDS: the log-weights stay
 // in LDS (ppw N_p floats); else they go to u_hbm [N] (context scratch, fully
-// rewritten).
+// rewritten).  lm_out, if not NULL, receives every PE's log-mass L^(m) beside
+// its record ([F M] doubles, contiguous for the master record's reduction).
 template <int HALF, int LIK, bool ULDS>
 __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const uint32_t ppw,
-                                          const uint32_t bid) {
+                                          const uint32_t bid, double *lm_out) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x;
@@ -416,6 +417,7 @@ __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const
             rec.lstar = ls;
             rec.total_q = Tq;
             a.rout[f * M + mq] = rec;
+            if (lm_out) lm_out[f * M + mq] = rec.log_mass;
             const Prologue *pq = L.pro + q;
             if (mq == 0) {
                 a.nex_used[f] = pq->nex;
@@ -448,8 +450,9 @@ __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const
 
 
 template <int HALF, int LIK, bool ULDS>
-__global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw) {
-    flex_body<HALF, LIK, ULDS>(a, u_hbm, ppw, blockIdx.x);
+__global__ __launch_bounds__(1024) void k_step_flex(StepArgs a, float *u_hbm, uint32_t ppw,
+                                                    double *lm_out) {
+    flex_body<HALF, LIK, ULDS>(a, u_hbm, ppw, blockIdx.x, lm_out);
 }
 
 // The context of workgroup `bid` in a batched launch: contexts own the
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(1024) void k_step_flex_batch(const StepArgs *args,
                                                           float *const *u, uint32_t ppw) {
     const uint32_t i = batch_context(first, n, blockIdx.x);
     const StepArgs a = args[i];
-    flex_body<HALF, LIK, ULDS>(a, u[i], ppw, blockIdx.x - first[i]);
+    flex_body<HALF, LIK, ULDS>(a, u[i], ppw, blockIdx.x - first[i], nullptr);
 }
 
 // ---------------------------------------------------------------- split PEs

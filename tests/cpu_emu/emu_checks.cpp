@@ -274,7 +274,8 @@ static int launch_flex(pf_ctx *c, const float *frame, float *u, uint32_t ppw, ui
     if (rc != PF_OK) return rc;
     StepArgs a = make_args(c, k, frame);
     void *fn = pick_flex_kernel(c->half, c->cfg.lik_mode, ulds);
-    void *args[] = {&a, &u, &ppw};
+    double *lm = nullptr;
+    void *args[] = {&a, &u, &ppw, &lm};
     const uint32_t grid = c->cfg.n_filters * ((c->cfg.n_pe + ppw - 1) / ppw);
     if (hipLaunchKernel(fn, dim3(grid), dim3(B), args,
                         flex_lds_bytes(ulds ? ppw * c->cfg.n_per_pe : 0), c->stream) != hipSuccess)
@@ -480,9 +481,10 @@ __global__ void k_master_ref(const pf_pe_record *rec, MasterRec *out, uint32_t M
                  out + blockIdx.x);
 }
 
-// k_master (every log-mass of a thread loaded before the reductions) against
-// master_block, bit for bit: random masses, PEs without mass, filters without
-// mass, one PE holding it all; ragged M up to PF_MAX_PE.
+// k_master (every log-mass of a thread loaded before the reductions), from
+// the records and from the compact log-masses, against master_block, bit for
+// bit: random masses, PEs without mass, filters without mass, one PE holding
+// it all; ragged M up to PF_MAX_PE.
 static int master_main() {
     struct MC { uint32_t F, M, np, mode, kind; };
     const MC cases[] = {{1, 1, 64, 1, 0},     {2, 3, 100, 1, 1},    {1, 255, 4096, 1, 0},
@@ -505,27 +507,41 @@ static int master_main() {
             rec[i].log_mass = L;
         }
         pf_pe_record *d_rec;
-        MasterRec *d_a, *d_b;
+        double *d_lm;
+        MasterRec *d_a, *d_b, *d_c;
         hipMalloc(&d_rec, n * sizeof(pf_pe_record));
+        hipMalloc(&d_lm, n * sizeof(double));
         hipMalloc(&d_a, mc.F * sizeof(MasterRec));
         hipMalloc(&d_b, mc.F * sizeof(MasterRec));
+        hipMalloc(&d_c, mc.F * sizeof(MasterRec));
         memcpy(d_rec, rec.data(), n * sizeof(pf_pe_record));
+        for (size_t i = 0; i < n; ++i) d_lm[i] = rec[i].log_mass;
         memset(d_a, 0xAB, mc.F * sizeof(MasterRec));
         memset(d_b, 0xCD, mc.F * sizeof(MasterRec));
+        memset(d_c, 0xEF, mc.F * sizeof(MasterRec));
         const uint32_t fixed_nex = mc.np / 10, cutoff = 990000;
-        hipLaunchKernelGGL(k_master, dim3(mc.F), dim3(kMasterThreads), 0, nullptr, d_rec, d_a,
-                           mc.M, mc.np, mc.mode, fixed_nex, cutoff);
+        const double *no_lm = nullptr;
+        // the library's choice of unrolling from the records, the widest one
+        // from the compact log-masses
+        check(launch_master(nullptr, mc.F, mc.M, mc.np, mc.mode, fixed_nex, cutoff, d_rec, no_lm,
+                            d_a), "launch_master");
+        hipLaunchKernelGGL(k_master<kMasterPerThread>, dim3(mc.F), dim3(kMasterThreads), 0,
+                           nullptr, d_rec, (const double *)d_lm, d_c, mc.M, mc.np, mc.mode,
+                           fixed_nex, cutoff);
         hipLaunchKernelGGL(k_master_ref, dim3(mc.F), dim3(kMasterThreads), 0, nullptr, d_rec, d_b,
                            mc.M, mc.np, mc.mode, fixed_nex, cutoff);
         hipDeviceSynchronize();
-        const bool eq = memcmp(d_a, d_b, mc.F * sizeof(MasterRec)) == 0;
+        const bool eq = memcmp(d_a, d_b, mc.F * sizeof(MasterRec)) == 0 &&
+                        memcmp(d_c, d_b, mc.F * sizeof(MasterRec)) == 0;
         fprintf(stderr, "master F=%u M=%u np=%u mode=%u kind=%u: %s (log W %.17g, N_ex %u)\n",
                 mc.F, mc.M, mc.np, mc.mode, mc.kind, eq ? "equal" : "DIFFERENT", d_a[0].lglob,
                 d_a[0].nex_next);
         bad += !eq;
         hipFree(d_rec);
+        hipFree(d_lm);
         hipFree(d_a);
         hipFree(d_b);
+        hipFree(d_c);
     }
     fprintf(stderr, bad ? "MASTER MISMATCH\n" : "MASTER EQUAL\n");
     return bad ? 2 : 0;
