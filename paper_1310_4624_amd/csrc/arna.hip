@@ -853,8 +853,9 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->adj_block = c->flex ? block_of(np) : c->block;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
-    c->lds = c->streamk ? flex_lds_bytes(0)
-                        : (c->flex ? flex_lds_bytes(c->ppw * np) : step_lds(np, lineage));
+    c->lds = c->streamk ? flex_lds_bytes(0, kTileCols)
+                        : (c->flex ? flex_lds_bytes(c->ppw * np, kSmallTile)
+                                   : step_lds(np, lineage));
     c->key0 = (uint32_t)cfg->seed;
     c->key1 = (uint32_t)(cfg->seed >> 32);
     c->fixed_nex = fixed_count(cfg->fixed_ratio, np);

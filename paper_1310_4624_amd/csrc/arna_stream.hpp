@@ -42,8 +42,20 @@ namespace {
 constexpr uint32_t kStreamBlock = 1024;   // threads of a streamed PE's workgroup
 constexpr uint32_t kMaxPesPerWg = 16;
 
+// Image tile edge of k_step_flex: 32 x 32 pixels for several PEs per
+// workgroup (ULDS), whose few particles per workgroup do not pay for loading
+// 64 x 64 (measured on MI355X at 2^20 particles, us per iteration, 64 / 32:
+// 8192 x 128 PEs 64.7 / 55.5 with 4 PEs per 256-thread workgroup, 4096 x 256
+// 48.2 / 46.0 with 8 per 512, 1024 x 1024 41.1 / 40.0 with 4 per 1024);
+// streamed and split PEs keep the step kernels' 64 x 64.  A patch that does
+// not fit the tile reads the frame, with the same result.  Rows are TS + 6
+// floats apart.
+constexpr int kSmallTile = 32;
+__host__ __device__ constexpr int tile_pitch(int ts) { return ts + 6; }
+static_assert(tile_pitch(kTileCols) == kTilePitch && kTileRows == kTileCols, "square tiles");
+
 struct FlexLds {
-    float *tile;       // [kTileRows][kTilePitch]
+    float *tile;       // [TS][tile_pitch(TS)]
     double *wsum;      // [16][6] wave sums (W, W x)
     float *wmax;       // [16] wave maxima of u
     uint32_t *wq;      // [16] wave totals of Q
@@ -51,16 +63,17 @@ struct FlexLds {
     Prologue *pro;     // [kMaxPesPerWg]
     float *u;          // [P N_p] log-weights (when they stay in LDS)
 };
-__host__ __device__ constexpr size_t flex_lds_bytes(uint32_t u_slots) {
-    return (size_t)kTileRows * kTilePitch * sizeof(float) + kMaxWaves * 6 * sizeof(double) +
+__host__ __device__ constexpr size_t flex_lds_bytes(uint32_t u_slots, int ts) {
+    return (size_t)ts * tile_pitch(ts) * sizeof(float) + kMaxWaves * 6 * sizeof(double) +
            kMaxWaves * sizeof(float) + kMaxWaves * sizeof(uint32_t) + 16 +
            kMaxPesPerWg * sizeof(Prologue) + (size_t)u_slots * sizeof(float);
 }
+template <int TS>
 __device__ __forceinline__ FlexLds flex_carve(unsigned char *base) {
     FlexLds l;
     size_t o = 0;
     l.tile = (float *)(base + o);
-    o += (size_t)kTileRows * kTilePitch * sizeof(float);
+    o += (size_t)TS * tile_pitch(TS) * sizeof(float);
     l.wsum = (double *)(base + o);
     o += kMaxWaves * 6 * sizeof(double);
     l.wmax = (float *)(base + o);
@@ -89,32 +102,31 @@ __device__ __forceinline__ uint32_t uni(uint32_t v) {
 }
 __device__ __forceinline__ float uni(float v) { return __uint_as_float(uni(__float_as_uint(v))); }
 
-// The image tile of a workgroup: 64 x 64 pixels of z - B around the estimate
+// The image tile of a workgroup: TS x TS pixels of z - B around the estimate
 // of k-1 moved one step (x + v), zero outside the image; off when the
 // estimate is not finite (a PE without mass).
 struct TileView {
     int tx0, ty0;
     bool on, inside;
 };
-template <bool POINT>
+template <bool POINT, int TS>
 __device__ __forceinline__ TileView load_tile(const StepArgs &a, const double *xh, float *tile,
                                               const uint32_t tid, const uint32_t B) {
     TileView v{0, 0, false, false};
     if (POINT) return v;
     const double cx = xh[0] + xh[2], cy = xh[1] + xh[3];
     if (fabs(cx) < 1e6 && fabs(cy) < 1e6) {   // false for NaN
-        v.tx0 = (int)floor(cx + 0.5) - kTileCols / 2;
-        v.ty0 = (int)floor(cy + 0.5) - kTileRows / 2;
-        v.on = v.tx0 < (int)a.lik.W && v.tx0 + kTileCols > 0 && v.ty0 < (int)a.lik.H &&
-               v.ty0 + kTileRows > 0;
-        v.inside = v.tx0 >= 0 && v.ty0 >= 0 && v.tx0 + kTileCols <= (int)a.lik.W &&
-                   v.ty0 + kTileRows <= (int)a.lik.H;
+        v.tx0 = (int)floor(cx + 0.5) - TS / 2;
+        v.ty0 = (int)floor(cy + 0.5) - TS / 2;
+        v.on = v.tx0 < (int)a.lik.W && v.tx0 + TS > 0 && v.ty0 < (int)a.lik.H && v.ty0 + TS > 0;
+        v.inside = v.tx0 >= 0 && v.ty0 >= 0 && v.tx0 + TS <= (int)a.lik.W &&
+                   v.ty0 + TS <= (int)a.lik.H;
     }
     if (v.on)
-        for (uint32_t idx = tid; idx < (uint32_t)(kTileRows * kTileCols); idx += B) {
-            const int uu = v.tx0 + (int)(idx % kTileCols), vv = v.ty0 + (int)(idx / kTileCols);
+        for (uint32_t idx = tid; idx < (uint32_t)(TS * TS); idx += B) {
+            const int uu = v.tx0 + (int)(idx % TS), vv = v.ty0 + (int)(idx / TS);
             const bool in = (unsigned)uu < (unsigned)a.lik.W && (unsigned)vv < (unsigned)a.lik.H;
-            tile[(idx / kTileCols) * kTilePitch + idx % kTileCols] =
+            tile[(idx / TS) * tile_pitch(TS) + idx % TS] =
                 in ? a.lik.img[(size_t)vv * a.lik.W + uu] - a.lik.bg : 0.f;
         }
     return v;
@@ -165,7 +177,7 @@ __device__ __forceinline__ Prologue uniform_prologue(const Prologue *pp) {
 // propagation, the likelihood, u = lambda + l to ub[s].  Returns the lane's
 // maximum of u.  Called by whole waves (a NaN log-likelihood sets the sticky
 // error bit through a wave vote).
-template <int HALF, int LIK>
+template <int HALF, int LIK, int TS>
 __device__ __forceinline__ float pass_a(const StepArgs &a, const Prologue &p, uint32_t f,
                                         uint32_t m, uint32_t s0, uint32_t s1, uint32_t step,
                                         float *ub, const float *tile, const TileView &tv) {
@@ -204,16 +216,16 @@ __device__ __forceinline__ float pass_a(const StepArgs &a, const Prologue &p, ui
             ell = loglik_point(x, a.lik, f);
         } else if (patch_origin<HALF>(x[0], x[1], a.lik.W, a.lik.H, u0, v0)) {
             const int du = u0 - tv.tx0, dv = v0 - tv.ty0;
-            if (tv.on && (unsigned)du <= (unsigned)(kTileCols - P) &&
-                (unsigned)dv <= (unsigned)(kTileRows - P)) {
-                const float *pix = tile + dv * kTilePitch + du;
+            if (tv.on && (unsigned)du <= (unsigned)(TS - P) &&
+                (unsigned)dv <= (unsigned)(TS - P)) {
+                constexpr int TP = tile_pitch(TS);
+                const float *pix = tile + dv * TP + du;
                 if (LIK == kLikPoisson)
-                    ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, kTilePitch, a.lik);
+                    ell = patch_loglik_poisson<HALF, kFromTile>(x, u0, v0, pix, TP, a.lik);
                 else
-                    ell = tv.inside ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix,
-                                                                          kTilePitch, a.lik)
-                                    : patch_loglik<HALF, kFromTile>(x, u0, v0, pix, kTilePitch,
-                                                                    a.lik);
+                    ell = tv.inside
+                              ? patch_loglik<HALF, kFromTileInside>(x, u0, v0, pix, TP, a.lik)
+                              : patch_loglik<HALF, kFromTile>(x, u0, v0, pix, TP, a.lik);
             } else if (u0 >= 0 && v0 >= 0 && u0 + P <= (int)a.lik.W && v0 + P <= (int)a.lik.H) {
                 const float *pix = a.lik.img + (size_t)v0 * a.lik.W + u0;
                 ell = (LIK == kLikPoisson)
@@ -341,7 +353,8 @@ __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const
     const uint32_t m = m0 + lp;
     const bool active = m < M;   // the same in every lane of a wave
     const uint32_t pe_base = (f * M + m) * np;
-    FlexLds L = flex_carve(smem);
+    constexpr int TS = ULDS ? kSmallTile : kTileCols;
+    FlexLds L = flex_carve<TS>(smem);
     float *ub = ULDS ? L.u + lp * np : u_hbm + pe_base;
     const DebugBufs *D = a.dbg;
     const bool trace = D && D->t_q;
@@ -354,14 +367,14 @@ __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const
         else
             prologue_wave(a, f, m, L.pro + lp, lane);
     }
-    const TileView tv = load_tile<POINT>(a, a.rin[f * M + m0].xhat, L.tile, tid, B);
+    const TileView tv = load_tile<POINT, TS>(a, a.rin[f * M + m0].xhat, L.tile, tid, B);
     __syncthreads();   // prologues and tile visible
 
     // ---- pass A (steps 3-5)
     float umax = -INFINITY;
     if (active) {
         const Prologue p = uniform_prologue(L.pro + lp);
-        umax = pass_a<HALF, LIK>(a, p, f, m, lt, np, tp, ub, L.tile, tv);
+        umax = pass_a<HALF, LIK, TS>(a, p, f, m, lt, np, tp, ub, L.tile, tv);
     }
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
@@ -503,7 +516,7 @@ struct SplitBufs {
     uint32_t G;        // segments per PE
 };
 
-__host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0); }
+__host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0, kTileCols); }
 
 // The segment's slot range and the PE's maximum of u (from the segment maxima).
 struct Segment {
@@ -537,13 +550,14 @@ __device__ __forceinline__ void split_weights_body(const StepArgs &a, const Spli
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve(smem);
+    FlexLds L = flex_carve<kTileCols>(smem);
     if (wave == 0) prologue_wave(a, sg.f, sg.m, L.pro, lane);
-    const TileView tv = load_tile<POINT>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
+    const TileView tv =
+        load_tile<POINT, kTileCols>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
     __syncthreads();   // prologue and tile visible
     const Prologue p = uniform_prologue(L.pro);
-    float umax = pass_a<HALF, LIK>(a, p, sg.f, sg.m, sg.s0 + tid, sg.s1, kSplitBlock,
-                                   sb.u + sg.pe_base, L.tile, tv);
+    float umax = pass_a<HALF, LIK, kTileCols>(a, p, sg.f, sg.m, sg.s0 + tid, sg.s1,
+                                              kSplitBlock, sb.u + sg.pe_base, L.tile, tv);
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
     __syncthreads();
@@ -575,7 +589,7 @@ __device__ __forceinline__ void split_totals_body(const StepArgs &a, const Split
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve(smem);
+    FlexLds L = flex_carve<kTileCols>(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     uint32_t c_lo, c_hi;
     wave_chunk(sg, wave, c_lo, c_hi);
@@ -598,7 +612,7 @@ __device__ __forceinline__ void split_ancestors_body(const StepArgs &a, const Sp
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve(smem);
+    FlexLds L = flex_carve<kTileCols>(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     // wave 0: the sum of the wave totals of the PE's earlier segments and of
     // this segment's earlier waves (exclusive prefix in (segment, wave)
