@@ -12,17 +12,18 @@
 // overlap instead of adding up over the two passes (maximum, then the sum of
 // exp(L - max)), and k_step_flex writes the log-masses side by side, so that
 // the read is contiguous rather than one 8-byte value per 56-byte record.
-// Measured on MI355X (us per launch, one filter; two passes over the records
-// with the loads issued as needed / this kernel): 512 PEs 5.0 / 4.5, 1024 5.9
-// / 4.8, 2048 7.8 / 6.6, 4096 11.8 / 7.8, 8192 19.7 / 9.9.  (1024 threads
-// instead of 256, from the records: 12.0 us at 8192 PEs, longer below.)
+// Measured on MI355X (us per launch, one filter, after k_step_flex): two
+// passes over the records by 256 threads with the loads issued as needed,
+// 5.0 at 512 PEs, 7.8 at 2048, 11.8 at 4096, 19.7 at 8192; this kernel with
+// 256 / 512 / 1024 threads, 5.2 / 5.3 / 6.6 at 2048 PEs, 7.8 / 6.1 / 7.7 at
+// 4096, 9.9 / 8.1 / 9.3 at 8192.
 #pragma once
 
 #include "arna_kernels.hpp"
 
 namespace {
 
-constexpr uint32_t kMasterThreads = 256;
+constexpr uint32_t kMasterThreads = 512;
 constexpr uint32_t kMasterPerThread = PF_MAX_PE / kMasterThreads;
 static_assert(kMasterPerThread * kMasterThreads == PF_MAX_PE, "PF_MAX_PE records per workgroup");
 
