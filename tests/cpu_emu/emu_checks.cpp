@@ -220,6 +220,8 @@ static int traj_main() {
         {1, 300, 64, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 11},    // more than 256 PEs
         {3, 5, 77, 128, 128, 1, 1, 9, 0, 0, 0.5f, 5.f, 1.f, 6},
         {1, 2, 5000, 96, 96, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 8},     // split PEs
+        {1, 520, 16, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 9},     // master records
+        {1, 530, 16, 64, 64, 1, 0, 9, 0, 0, 0.1f, 5.f, 2.f, 10, 4}, // and k_step_flex
     };
     std::mt19937_64 rng(7);
     for (const Case &cs : cases) {

@@ -37,6 +37,13 @@ CASES = {
                             mode=1, lik_mode=0, pes_per_wg=4, seed=45),
     "split_1x4x9000": dict(BASE, n_filters=1, n_pe=4, n_per_pe=9000, width=128, height=128,
                            mode=1, lik_mode=0, seed=46),
+    # 512 PEs or more: the master step once per filter after every step
+    # (k_master, from the records after k_step, from the log-masses k_step_flex
+    # writes beside them), rows from k_global
+    "master_1x600x64": dict(BASE, n_filters=1, n_pe=600, n_per_pe=64, width=128, height=128,
+                            mode=1, lik_mode=0, seed=47),
+    "master_grouped_2x1100x50": dict(BASE, n_filters=2, n_pe=1100, n_per_pe=50, width=128,
+                                     height=128, mode=1, lik_mode=0, pes_per_wg=4, seed=48),
 }
 KEYS = ("x_global", "log_mass_glob", "pe_eff", "n_ex", "n_ex_next", "log_z_inc")
 
