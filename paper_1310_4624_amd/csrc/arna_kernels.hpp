@@ -63,9 +63,11 @@ struct StepArgs {
     uint32_t *nex_rec;                  // [F] N_ex of this iteration, kept for the adjoint; or NULL
     const uint32_t *force_nex;          // [F] N_ex to use instead of step 2's, or NULL
     const uint32_t *force_anc;          // [N] ancestors to use instead of step 7's, or NULL
-    // master steps (many PEs): of k-1, read by the prologue, and of k, written
-    // by the last workgroup of each filter to finish; NULL: every PE
-    // recomputes the master step from the M records
+    // master steps (many PEs): of k-1, read by the prologue (NULL: every PE
+    // recomputes it from the M records), and of k, written by the last
+    // workgroup of each filter to finish (NULL: not written; the library
+    // leaves it NULL and launches k_master after the step, which measured
+    // faster than every workgroup's release before counting itself in)
     const MasterRec *min;
     MasterRec *mout;
     uint32_t *arrive;                   // [F] workgroups of the filter done with k
