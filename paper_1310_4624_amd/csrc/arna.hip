@@ -853,7 +853,7 @@ int pf_init(const pf_config *cfg, const float *truth, pf_ctx **out) {
     c->adj_block = c->flex ? block_of(np) : c->block;
     const bool lineage = (cfg->debug & PF_DEBUG_LINEAGE) != 0;
     const bool trace = (cfg->debug & PF_DEBUG_TRACE) != 0;
-    c->lds = c->streamk ? flex_lds_bytes(0, kTileCols)
+    c->lds = c->streamk ? flex_lds_bytes(0, kSmallTile)
                         : (c->flex ? flex_lds_bytes(c->ppw * np, kSmallTile)
                                    : step_lds(np, lineage));
     c->key0 = (uint32_t)cfg->seed;

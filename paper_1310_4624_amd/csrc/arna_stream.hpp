@@ -42,14 +42,16 @@ namespace {
 constexpr uint32_t kStreamBlock = 1024;   // threads of a streamed PE's workgroup
 constexpr uint32_t kMaxPesPerWg = 16;
 
-// Image tile edge of k_step_flex: 32 x 32 pixels for several PEs per
-// workgroup (ULDS), whose few particles per workgroup do not pay for loading
-// 64 x 64 (measured on MI355X at 2^20 particles, us per iteration, 64 / 32:
-// 8192 x 128 PEs 64.7 / 55.5 with 4 PEs per 256-thread workgroup, 4096 x 256
-// 48.2 / 46.0 with 8 per 512, 1024 x 1024 41.1 / 40.0 with 4 per 1024);
-// streamed and split PEs keep the step kernels' 64 x 64.  A patch that does
-// not fit the tile reads the frame, with the same result.  Rows are TS + 6
-// floats apart.
+// Image tile edge of k_step_flex and the split kernels: 32 x 32 pixels, where
+// the step kernels load 64 x 64; the workgroups here hold few particles per
+// thread (several small PEs, or a PE's segment), for which loading 4096
+// pixels costs more than the frame reads of the patches that do not fit a
+// smaller tile (with the same result).  Measured on MI355X, us per iteration,
+// 64 / 32: at 2^20 particles, 8192 x 128 PEs 64.7 / 55.5 with 4 PEs per
+// 256-thread workgroup, 4096 x 256 48.2 / 46.0 with 8 per 512, 1024 x 1024
+// 41.1 / 40.0 with 4 per 1024; split, 16 x 65536 40.8 / 38.6, 64 x 16384
+// 43.2 / 41.1, 128 x 8192 43.9 / 41.8; one streamed PE per workgroup, 256 x
+// 8192 62.0 / 60.6, 512 x 8192 113.6 / 112.3.  Rows are TS + 6 floats apart.
 constexpr int kSmallTile = 32;
 __host__ __device__ constexpr int tile_pitch(int ts) { return ts + 6; }
 static_assert(tile_pitch(kTileCols) == kTilePitch && kTileRows == kTileCols, "square tiles");
@@ -353,7 +355,7 @@ __device__ __forceinline__ void flex_body(const StepArgs &a, float *u_hbm, const
     const uint32_t m = m0 + lp;
     const bool active = m < M;   // the same in every lane of a wave
     const uint32_t pe_base = (f * M + m) * np;
-    constexpr int TS = ULDS ? kSmallTile : kTileCols;
+    constexpr int TS = kSmallTile;
     FlexLds L = flex_carve<TS>(smem);
     float *ub = ULDS ? L.u + lp * np : u_hbm + pe_base;
     const DebugBufs *D = a.dbg;
@@ -516,7 +518,7 @@ struct SplitBufs {
     uint32_t G;        // segments per PE
 };
 
-__host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0, kTileCols); }
+__host__ __device__ constexpr size_t split_lds_bytes() { return flex_lds_bytes(0, kSmallTile); }
 
 // The segment's slot range and the PE's maximum of u (from the segment maxima).
 struct Segment {
@@ -550,13 +552,13 @@ __device__ __forceinline__ void split_weights_body(const StepArgs &a, const Spli
     constexpr bool POINT = LIK == kLikPoint;
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve<kTileCols>(smem);
+    FlexLds L = flex_carve<kSmallTile>(smem);
     if (wave == 0) prologue_wave(a, sg.f, sg.m, L.pro, lane);
     const TileView tv =
-        load_tile<POINT, kTileCols>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
+        load_tile<POINT, kSmallTile>(a, a.rin[sg.pe].xhat, L.tile, tid, kSplitBlock);
     __syncthreads();   // prologue and tile visible
     const Prologue p = uniform_prologue(L.pro);
-    float umax = pass_a<HALF, LIK, kTileCols>(a, p, sg.f, sg.m, sg.s0 + tid, sg.s1,
+    float umax = pass_a<HALF, LIK, kSmallTile>(a, p, sg.f, sg.m, sg.s0 + tid, sg.s1,
                                               kSplitBlock, sb.u + sg.pe_base, L.tile, tv);
     umax = wave_max_f32(umax);
     if (lane == 0) L.wmax[wave] = umax;
@@ -589,7 +591,7 @@ __device__ __forceinline__ void split_totals_body(const StepArgs &a, const Split
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve<kTileCols>(smem);
+    FlexLds L = flex_carve<kSmallTile>(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     uint32_t c_lo, c_hi;
     wave_chunk(sg, wave, c_lo, c_hi);
@@ -612,7 +614,7 @@ __device__ __forceinline__ void split_ancestors_body(const StepArgs &a, const Sp
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const Segment sg = segment_of(a, sb, bid);
-    FlexLds L = flex_carve<kTileCols>(smem);
+    FlexLds L = flex_carve<kSmallTile>(smem);
     const float lstar = pe_max_u(sb, sg.pe);
     // wave 0: the sum of the wave totals of the PE's earlier segments and of
     // this segment's earlier waves (exclusive prefix in (segment, wave)

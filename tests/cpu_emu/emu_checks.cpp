@@ -280,8 +280,7 @@ static int launch_flex(pf_ctx *c, const float *frame, float *u, uint32_t ppw, ui
     void *args[] = {&a, &u, &ppw, &lm};
     const uint32_t grid = c->cfg.n_filters * ((c->cfg.n_pe + ppw - 1) / ppw);
     if (hipLaunchKernel(fn, dim3(grid), dim3(B), args,
-                        ulds ? flex_lds_bytes(ppw * c->cfg.n_per_pe, kSmallTile)
-                             : flex_lds_bytes(0, kTileCols),
+                        flex_lds_bytes(ulds ? ppw * c->cfg.n_per_pe : 0, kSmallTile),
                         c->stream) != hipSuccess)
         return PF_EHIP;
     advance(c, k);
