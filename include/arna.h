@@ -241,8 +241,10 @@ int pf_estimate(pf_ctx *c, pf_estimate_t *out);
  * variant (slots per thread, workgroup size, the 9 x 9 patch with Gaussian or
  * Poisson noise, or point data) instead of one launch per context; the work
  * of each workgroup is exactly that of pf_step, so the results are bitwise
- * those of separate pf_run calls.  Contexts of other patch sizes are stepped
- * one by one inside the same run.  The contexts must use one stream and stay
+ * those of separate pf_run calls.  Contexts of other patch sizes, and
+ * contexts of 512 or more PEs per filter (whose iterations end with a
+ * once-per-filter master step launch, which a group does not have) are
+ * stepped one by one inside the same run.  The contexts must use one stream and stay
  * alive until pf_batch_destroy; the batch owns only its launch tables. */
 typedef struct pf_batch pf_batch;
 int pf_batch_create(pf_ctx *const *ctxs, uint32_t n, pf_batch **out);
