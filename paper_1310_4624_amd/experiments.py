@@ -24,7 +24,7 @@ import sys
 import numpy as np
 
 from . import synth
-from .tracker import Tracker
+from .tracker import TRAJ_RECORD_BYTES, Tracker, trajectory
 
 MODES = {"arna": (1, 0.1), "rna0": (0, 0.0), "rna10": (0, 0.1), "rna50": (0, 0.5)}
 
@@ -73,17 +73,19 @@ def tracking(mode: str, seq_seed: int = 1000, filter_seed: int = 1, steps: int =
     cfg = synth.filter_config(wl, mode=mflag, fixed_ratio=ratio, seed=filter_seed, **over)
     seq = seq if seq is not None else synth.make_sequence(wl, seed=seq_seed, frames=steps,
                                                           q_true=q_true)
+    import torch
     frames = _frames(seq)
     F = cfg["n_filters"]
+    K = min(steps, seq.frames.shape[0])
     tr = Tracker(cfg, seq.initial_truth()[:F])
-    err2, n_ex = [], []
-    for k in range(1, min(steps, seq.frames.shape[0]) + 1):
-        tr.step(frames[k - 1])
-        est = tr.estimate()
-        err2.append(np.sum((est["x_global"][:, :2] - seq.truth[k, :F, :2]) ** 2, axis=1))
-        n_ex.append(est["n_ex"].tolist())
+    # the master step of every iteration (Alg. 3 steps 9-10) to a device
+    # trajectory, read back once: its rows are the stepwise estimates
+    traj = torch.zeros(K * F * TRAJ_RECORD_BYTES, dtype=torch.uint8, device=frames.device)
+    tr.run_traj(frames[:K], traj)
+    rows = trajectory(traj, K, F)
     tr.close()
-    err2 = np.array(err2)
+    err2 = np.sum((rows["xhat"][:, :, :2] - seq.truth[1:K + 1, :F, :2]) ** 2, axis=2)
+    n_ex = rows["n_ex"]
     return dict(mode=mode, workload=wl, n_pe=cfg["n_pe"], n_per_pe=cfg["n_per_pe"],
                 q_true=q_true if q_true is not None
                 else synth.WORKLOADS[wl]["seq"].get("q_true", cfg["q"]),
