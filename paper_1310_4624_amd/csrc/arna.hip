@@ -583,7 +583,7 @@ StepArgs make_args(pf_ctx *c, uint64_t k, const float *frame, pf_master_t *traj_
     a.lin_in = (uint32_t)c->cur;
     a.err = c->err;
     a.nex_used = c->nex_used;
-    // (many PEs or split PEs: k_global writes the rows)
+    // (many PEs: k_master writes the rows; split PEs: k_global_wave)
     a.traj_prev = (c->mrec[0] || c->split) ? nullptr : traj_prev;
     return a;
 }
@@ -607,7 +607,11 @@ void advance(pf_ctx *c, uint64_t k) {
     c->exchanged = false;
 }
 
-int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr) {
+// traj_prev: the trajectory row of iteration k - 1, written by the step's
+// prologue (contexts without master records); row: that of iteration k,
+// written with the master record after the step (contexts with them).
+int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr,
+                pf_master_t *row = nullptr) {
     const uint64_t k = c->step + 1;
     if (k > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
     if (c->g_cap && c->g_len >= c->g_cap) return PF_ESTATE;   // tape full
@@ -635,7 +639,7 @@ int launch_step(pf_ctx *c, const float *frame, pf_master_t *traj_prev = nullptr)
         // (k_step_flex also wrote their log-masses side by side)
         HIP_OK(launch_master(c->stream, c->cfg.n_filters, c->cfg.n_pe, c->cfg.n_per_pe,
                              c->cfg.mode, c->fixed_nex, c->cutoff_ppm, a.rout, c->lm,
-                             c->mrec[1 - c->cur]));
+                             c->mrec[1 - c->cur], row, c->nex_used, k));
     }
     advance(c, k);
     return PF_OK;
@@ -669,24 +673,28 @@ bool run_allowed(const pf_ctx *c) {
 // to out[F].
 int launch_global(pf_ctx *c, pf_master_t *out) {
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
-    // fewer PEs: one wave per filter, in the order of the step's prologue
-    if (!c->mrec[0])
+    // without master records: one wave per filter, in the order of the step's
+    // prologue; with them: k_master's order (from the records; no record is
+    // written), the rows a trajectory run gets after every step
+    if (!c->mrec[0]) {
         hipLaunchKernelGGL(k_global_wave, dim3(c->cfg.n_filters), dim3(kWave), 0, c->stream,
                            cur_rec(c), out, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
                            c->fixed_nex, c->cutoff_ppm, (const uint32_t *)c->nex_used,
                            (uint64_t)c->step);
-    else
-        hipLaunchKernelGGL(k_global, dim3(c->cfg.n_filters), dim3(256), 0, c->stream, cur_rec(c),
-                           out, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode, c->fixed_nex,
-                           c->cutoff_ppm, (const uint32_t *)c->nex_used, (uint64_t)c->step);
-    HIP_OK(hipGetLastError());
+        HIP_OK(hipGetLastError());
+        return PF_OK;
+    }
+    HIP_OK(launch_master(c->stream, c->cfg.n_filters, c->cfg.n_pe, c->cfg.n_per_pe, c->cfg.mode,
+                         c->fixed_nex, c->cutoff_ppm, cur_rec(c), nullptr, nullptr, out,
+                         c->nex_used, c->step));
     return PF_OK;
 }
 
 // With traj, the master step of every iteration goes to traj[i][F]: without
 // master records the step of iteration i + 1 writes row i from its prologue
-// and one k_global_wave launch after the run writes the last row; with them
-// (and for split PEs), a global-estimate launch follows every step.  Either way the
+// and one k_global_wave launch after the run writes the last row; with them,
+// the k_master launch after every step writes its row; for split PEs, a
+// k_global_wave launch follows every step.  Either way the
 // iterations run one launch each.
 int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float *ms_out,
               pf_master_t *traj = nullptr) {
@@ -730,8 +738,11 @@ int run_steps(pf_ctx *c, const float *frames, uint32_t n, uint64_t stride, float
         if (len == 1) {
             const size_t F = c->cfg.n_filters;
             const bool fused = traj && !c->mrec[0] && !c->split;
-            rc = launch_step(c, frame, (fused && done) ? traj + (size_t)(done - 1) * F : nullptr);
-            if (rc == PF_OK && traj && !fused) rc = launch_global(c, traj + (size_t)done * F);
+            pf_master_t *row = (traj && c->mrec[0]) ? traj + (size_t)done * F : nullptr;
+            rc = launch_step(c, frame, (fused && done) ? traj + (size_t)(done - 1) * F : nullptr,
+                             row);
+            if (rc == PF_OK && traj && !fused && !row)
+                rc = launch_global(c, traj + (size_t)done * F);
         } else {
             RunPrep pr;
             memset(&pr, 0, sizeof(pr));

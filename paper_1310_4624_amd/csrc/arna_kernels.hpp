@@ -1056,51 +1056,14 @@ __global__ void k_identity(uint16_t *anc, uint32_t N, uint32_t np) {
     if (g < N) anc[g] = (uint16_t)(g % np);
 }
 
-// Master step of iteration k (Alg. 3, steps 9-10) for reporting: W_k, the
-// global estimate x_k = sum_m W^(m) x^m / W_k, PE_eff, the next N_ex and the
-// likelihood increment; n_ex is the N_ex iteration k used (nex_used[f]).
-__global__ __launch_bounds__(256) void k_global(const pf_pe_record *rec, pf_master_t *est,
-                                                uint32_t M, uint32_t np, uint32_t mode,
-                                                uint32_t fixed_nex, uint32_t cutoff_ppm,
-                                                const uint32_t *nex_used, uint64_t step) {
-    __shared__ double red[kRedDoubles];
-    const uint32_t f = blockIdx.x;
-    const pf_pe_record *R = rec + (size_t)f * M;
-    double lmax = -INFINITY;
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) lmax = fmax(lmax, R[i].log_mass);
-    lmax = block_max_d(lmax, red);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    uint64_t sd[2] = {0, 0};
-    if (lmax != -INFINITY) {
-        for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-            const double e = exp(R[i].log_mass - lmax);
-            const uint64_t P = (uint64_t)floor(e * 1048576.0);
-            sd[0] += P;
-            sd[1] += P * P;
-            acc[0] += e;
-            if (e > 0.0)
-                for (int c = 0; c < 5; ++c) acc[1 + c] += e * R[i].xhat[c];
-        }
-    }
-    block_sum<6>(acc, red);
-    block_sum_u64(sd, (uint64_t *)red);
-    if (threadIdx.x == 0) {
-        pf_master_t o;
-        o.log_mass_glob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
-        for (int c = 0; c < 5; ++c) o.xhat[c] = acc[1 + c] / acc[0];
-        o.pe_eff = sd[1] ? (double)sd[0] * (double)sd[0] / (double)sd[1] : 0.0;
-        o.log_z_inc = o.log_mass_glob - log((double)np);
-        o.n_ex = nex_used ? nex_used[f] : 0u;
-        o.n_ex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
-        o.step = step;
-        est[f] = o;
-    }
-}
-
-// k_global for contexts without master records, one wave per filter: the master step in
-// the order of prologue_wave's sums (records in chunks of 64 lanes, the first
-// kCached chunks, then the rest; wave butterflies), so that a trajectory row
-// written by the prologue and this kernel's record agree bit for bit.
+// Master step of iteration k (Alg. 3, steps 9-10) for reporting, for
+// contexts without master records (with them k_master computes it), one wave
+// per filter: W_k, the global estimate x_k = sum_m W^(m) x^m / W_k, PE_eff,
+// the next N_ex and the likelihood increment, n_ex the N_ex iteration k used
+// (nex_used[f]).  The sums run in the order of prologue_wave's (records in
+// chunks of 64 lanes, the first kCached chunks, then the rest; wave
+// butterflies), so that a trajectory row written by the prologue and this
+// kernel's record agree bit for bit.
 __global__ __launch_bounds__(64) void k_global_wave(const pf_pe_record *rec, pf_master_t *est,
                                                     uint32_t M, uint32_t np, uint32_t mode,
                                                     uint32_t fixed_nex, uint32_t cutoff_ppm,

@@ -28,16 +28,19 @@ constexpr uint32_t kMasterPerThread = PF_MAX_PE / kMasterThreads;
 static_assert(kMasterPerThread * kMasterThreads == PF_MAX_PE, "PF_MAX_PE records per workgroup");
 
 // Master record of filter blockIdx.x from its M <= PER kMasterThreads records
-// (block of kMasterThreads threads).  With lm (the log-masses [F M] the step
-// wrote beside the records) the reads are contiguous: the same values, the
-// same record.  PER only sizes the unrolled loads: every PER covering M gives
-// the same record.
+// (block of kMasterThreads threads) to out (if not NULL) and, with row, the
+// whole master step of the iteration (Alg. 3 steps 9-10: also x_k = sum_m
+// W^(m) x^m / W_k, PE_eff, the increment of log Z, N_ex used, from nex_used)
+// to row[f].  With lm (the log-masses [F M] the step wrote beside the
+// records) their reads are contiguous: the same values, the same record.  PER
+// only sizes the unrolled loads: every PER covering M gives the same record,
+// and the record is the same with or without the row (the sums of W and of
+// W x^m are reduced component by component in the same order).
 template <uint32_t PER>
-__global__ __launch_bounds__(kMasterThreads) void k_master(const pf_pe_record *rec,
-                                                           const double *lm, MasterRec *out,
-                                                           uint32_t M, uint32_t np, uint32_t mode,
-                                                           uint32_t fixed_nex,
-                                                           uint32_t cutoff_ppm) {
+__global__ __launch_bounds__(kMasterThreads) void k_master(
+    const pf_pe_record *rec, const double *lm, MasterRec *out, pf_master_t *row,
+    const uint32_t *nex_used, uint64_t step, uint32_t M, uint32_t np, uint32_t mode,
+    uint32_t fixed_nex, uint32_t cutoff_ppm) {
     __shared__ double red[kRedDoubles];
     const size_t base = (size_t)blockIdx.x * M;
     const uint32_t tid = threadIdx.x;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(kMasterThreads) void k_master(const pf_pe_record *r
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) lmax = fmax(lmax, L[j]);
     lmax = block_max_d(lmax, red);
-    double acc[1] = {0.0};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
     uint64_t sd[2] = {0, 0};
     if (lmax != -INFINITY) {
 #pragma unroll
@@ -70,36 +73,74 @@ __global__ __launch_bounds__(kMasterThreads) void k_master(const pf_pe_record *r
                 acc[0] += e;
                 sd[0] += P;
                 sd[1] += P * P;
+                L[j] = e;   // (kept for the row)
+            }
+        }
+        if (row) {
+#pragma unroll 4
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t i = tid + j * kMasterThreads;
+                if (i < M && L[j] > 0.0) {
+                    const double *x = rec[base + i].xhat;
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[1 + c] += L[j] * x[c];
+                }
             }
         }
     }
-    block_sum<1>(acc, red);
+    if (row) {
+        block_sum<6>(acc, red);
+    } else {
+        double a1[1] = {acc[0]};
+        block_sum<1>(a1, red);
+        acc[0] = a1[0];
+    }
     block_sum_u64(sd, (uint64_t *)red);
     if (tid == 0) {
-        MasterRec r;
-        r.lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
-        r.nex_next = exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
-        r.pad = 0;
-        out[blockIdx.x] = r;
+        const uint32_t f = blockIdx.x;
+        const double lglob = (lmax == -INFINITY) ? -INFINITY : lmax + log(acc[0]);
+        const uint32_t nex_next =
+            exchange_count(sd[0], sd[1], M, np, mode, 0, fixed_nex, 0, cutoff_ppm);
+        if (out) {
+            MasterRec r;
+            r.lglob = lglob;
+            r.nex_next = nex_next;
+            r.pad = 0;
+            out[f] = r;
+        }
+        if (row) {
+            pf_master_t o;
+            o.log_mass_glob = lglob;
+            for (int c = 0; c < 5; ++c) o.xhat[c] = acc[1 + c] / acc[0];
+            o.pe_eff = sd[1] ? (double)sd[0] * (double)sd[0] / (double)sd[1] : 0.0;
+            o.log_z_inc = lglob - log((double)np);
+            o.n_ex = nex_used ? nex_used[f] : 0u;
+            o.n_ex_next = nex_next;
+            o.step = step;
+            row[f] = o;
+        }
     }
 }
 
-// The master records of F filters of M PEs each on stream s: the smallest
-// unrolling that covers M (a short kernel for few PEs).
+// The master records (out, if not NULL) and master steps (row, if not NULL)
+// of F filters of M PEs each on stream s: the smallest unrolling that covers
+// M (a short kernel for few PEs).
 inline hipError_t launch_master(hipStream_t s, uint32_t F, uint32_t M, uint32_t np,
                                 uint32_t mode, uint32_t fixed_nex, uint32_t cutoff_ppm,
-                                const pf_pe_record *rec, const double *lm, MasterRec *out) {
+                                const pf_pe_record *rec, const double *lm, MasterRec *out,
+                                pf_master_t *row = nullptr, const uint32_t *nex_used = nullptr,
+                                uint64_t step = 0) {
     (void)hipGetLastError();   // clear errors of earlier, unrelated calls
     const dim3 grid(F), block(kMasterThreads);
     if (M <= 2 * kMasterThreads)
-        hipLaunchKernelGGL(k_master<2>, grid, block, 0, s, rec, lm, out, M, np, mode, fixed_nex,
-                           cutoff_ppm);
+        hipLaunchKernelGGL(k_master<2>, grid, block, 0, s, rec, lm, out, row, nex_used, step, M,
+                           np, mode, fixed_nex, cutoff_ppm);
     else if (M <= 8 * kMasterThreads)
-        hipLaunchKernelGGL(k_master<8>, grid, block, 0, s, rec, lm, out, M, np, mode, fixed_nex,
-                           cutoff_ppm);
+        hipLaunchKernelGGL(k_master<8>, grid, block, 0, s, rec, lm, out, row, nex_used, step, M,
+                           np, mode, fixed_nex, cutoff_ppm);
     else
-        hipLaunchKernelGGL(k_master<kMasterPerThread>, grid, block, 0, s, rec, lm, out, M, np,
-                           mode, fixed_nex, cutoff_ppm);
+        hipLaunchKernelGGL(k_master<kMasterPerThread>, grid, block, 0, s, rec, lm, out, row,
+                           nex_used, step, M, np, mode, fixed_nex, cutoff_ppm);
     return hipGetLastError();
 }
 

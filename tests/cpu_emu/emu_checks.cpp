@@ -485,9 +485,10 @@ __global__ void k_master_ref(const pf_pe_record *rec, MasterRec *out, uint32_t M
 }
 
 // k_master (every log-mass of a thread loaded before the reductions), from
-// the records and from the compact log-masses, against master_block, bit for
-// bit: random masses, PEs without mass, filters without mass, one PE holding
-// it all; ragged M up to PF_MAX_PE.
+// the records and from the compact log-masses (the latter also writing the
+// master step's row), against master_block, bit for bit: random masses, PEs
+// without mass, filters without mass, one PE holding it all; ragged M up to
+// PF_MAX_PE.  The row against the master step in FP64 on the host.
 static int master_main() {
     struct MC { uint32_t F, M, np, mode, kind; };
     const MC cases[] = {{1, 1, 64, 1, 0},     {2, 3, 100, 1, 1},    {1, 255, 4096, 1, 0},
@@ -508,10 +509,16 @@ static int master_main() {
             if (mc.kind == 2) L = -INFINITY;                      // no mass at all
             if (mc.kind == 3) L = (i % mc.M == 17) ? 0.0 : -800.0;
             rec[i].log_mass = L;
+            for (int c = 0; c < 5; ++c) rec[i].xhat[c] = 50.0 + 10.0 * Nd(rng);
         }
         pf_pe_record *d_rec;
         double *d_lm;
         MasterRec *d_a, *d_b, *d_c;
+        pf_master_t *d_row;
+        uint32_t *d_nex;
+        hipMalloc(&d_row, mc.F * sizeof(pf_master_t));
+        hipMalloc(&d_nex, mc.F * sizeof(uint32_t));
+        for (uint32_t f = 0; f < mc.F; ++f) d_nex[f] = 7 + f;
         hipMalloc(&d_rec, n * sizeof(pf_pe_record));
         hipMalloc(&d_lm, n * sizeof(double));
         hipMalloc(&d_a, mc.F * sizeof(MasterRec));
@@ -529,13 +536,41 @@ static int master_main() {
         check(launch_master(nullptr, mc.F, mc.M, mc.np, mc.mode, fixed_nex, cutoff, d_rec, no_lm,
                             d_a), "launch_master");
         hipLaunchKernelGGL(k_master<kMasterPerThread>, dim3(mc.F), dim3(kMasterThreads), 0,
-                           nullptr, d_rec, (const double *)d_lm, d_c, mc.M, mc.np, mc.mode,
+                           nullptr, d_rec, (const double *)d_lm, d_c, d_row,
+                           (const uint32_t *)d_nex, (uint64_t)42, mc.M, mc.np, mc.mode,
                            fixed_nex, cutoff);
         hipLaunchKernelGGL(k_master_ref, dim3(mc.F), dim3(kMasterThreads), 0, nullptr, d_rec, d_b,
                            mc.M, mc.np, mc.mode, fixed_nex, cutoff);
         hipDeviceSynchronize();
-        const bool eq = memcmp(d_a, d_b, mc.F * sizeof(MasterRec)) == 0 &&
-                        memcmp(d_c, d_b, mc.F * sizeof(MasterRec)) == 0;
+        bool eq = memcmp(d_a, d_b, mc.F * sizeof(MasterRec)) == 0 &&
+                  memcmp(d_c, d_b, mc.F * sizeof(MasterRec)) == 0;
+        for (uint32_t f = 0; f < mc.F; ++f) {   // the row, in FP64 on the host
+            const pf_pe_record *R = rec.data() + (size_t)f * mc.M;
+            double lmax = -INFINITY, W = 0, X[5] = {0, 0, 0, 0, 0};
+            uint64_t S = 0, D = 0;
+            for (uint32_t i = 0; i < mc.M; ++i) lmax = std::max(lmax, R[i].log_mass);
+            for (uint32_t i = 0; lmax != -INFINITY && i < mc.M; ++i) {
+                const double e = exp(R[i].log_mass - lmax);
+                const uint64_t P = (uint64_t)floor(e * 1048576.0);
+                W += e;
+                S += P;
+                D += P * P;
+                for (int c = 0; e > 0.0 && c < 5; ++c) X[c] += e * R[i].xhat[c];
+            }
+            const pf_master_t &o = d_row[f];
+            const double lg = lmax == -INFINITY ? -INFINITY : lmax + log(W);
+            bool ok = o.step == 42 && o.n_ex == 7 + f && o.n_ex_next == d_b[f].nex_next &&
+                      (o.log_mass_glob == d_b[f].lglob) &&
+                      (lmax == -INFINITY ? o.log_mass_glob == -INFINITY
+                                         : fabs(o.log_mass_glob - lg) <= 1e-12 * (1 + fabs(lg))) &&
+                      o.pe_eff == (D ? (double)S * (double)S / (double)D : 0.0);
+            for (int c = 0; lmax != -INFINITY && c < 5; ++c)
+                ok = ok && fabs(o.xhat[c] - X[c] / W) <= 1e-12 * (1 + fabs(X[c] / W));
+            if (!ok)
+                fprintf(stderr, "  row of filter %u: log W %.17g / %.17g, PE_eff %.17g, x %.17g / %.17g\n",
+                        f, o.log_mass_glob, lg, o.pe_eff, o.xhat[0], X[0] / W);
+            eq = eq && ok;
+        }
         fprintf(stderr, "master F=%u M=%u np=%u mode=%u kind=%u: %s (log W %.17g, N_ex %u)\n",
                 mc.F, mc.M, mc.np, mc.mode, mc.kind, eq ? "equal" : "DIFFERENT", d_a[0].lglob,
                 d_a[0].nex_next);
@@ -545,6 +580,8 @@ static int master_main() {
         hipFree(d_a);
         hipFree(d_b);
         hipFree(d_c);
+        hipFree(d_row);
+        hipFree(d_nex);
     }
     fprintf(stderr, bad ? "MASTER MISMATCH\n" : "MASTER EQUAL\n");
     return bad ? 2 : 0;
