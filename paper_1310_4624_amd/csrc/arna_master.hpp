@@ -76,8 +76,8 @@ __global__ __launch_bounds__(kMasterThreads) void k_master(
                 L[j] = e;   // (kept for the row)
             }
         }
-        if (row) {
-#pragma unroll 4
+        if (row) {   // (fully unrolled: every load in flight at once)
+#pragma unroll
             for (uint32_t j = 0; j < PER; ++j) {
                 const uint32_t i = tid + j * kMasterThreads;
                 if (i < M && L[j] > 0.0) {
