@@ -40,6 +40,11 @@ CASES = {
     # forward iterations with several PEs per workgroup (the adjoint is the same)
     "grouped_arna_2x8x128": dict(over=dict(mode=O.MODE_ARNA, n_filters=2, n_pe=8, n_per_pe=128,
                                            pes_per_wg=4), frames=8),
+    # 512 PEs or more: the forward steps take the master step from k_master,
+    # the reverse sweep recomputes it from the records
+    "master_arna_600x64": dict(over=dict(mode=O.MODE_ARNA, n_pe=600, n_per_pe=64), frames=6),
+    "master_grouped_arna_600x64": dict(over=dict(mode=O.MODE_ARNA, n_pe=600, n_per_pe=64,
+                                                 pes_per_wg=4), frames=6),
     # the differentiable workload's shape: 2^20 particles over 256 PEs, 512 x 512
     "c5_arna_256x4096": dict(workload="arna_grad_512_256x4096", over={}, frames=12),
 }
