@@ -44,6 +44,11 @@ def _cases():
              seed=12),
         dict(base, n_filters=1, n_pe=2, n_per_pe=4500, width=64, height=64, mode=1, lik_mode=2,
              background=10.0, seed=13),
+        # 512 PEs or more: master records, stepped one by one inside the run
+        dict(base, n_filters=1, n_pe=600, n_per_pe=16, width=96, height=80, mode=1, lik_mode=0,
+             seed=14),
+        dict(base, n_filters=2, n_pe=520, n_per_pe=20, width=96, height=80, mode=1, lik_mode=0,
+             pes_per_wg=4, seed=15),
     ]
 
 
